@@ -1,0 +1,497 @@
+// The C-ABI of libmlmc: argument validation, per-device state, constants, dispatch.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "internal.h"
+#include "mlp.h"
+
+namespace mlmc {
+
+bool build_l2_table(int degree, double out[16][4]);
+hipError_t launch_level_f64(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+hipError_t launch_level_f32(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+hipError_t launch_level_f16(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+
+hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s) {
+    switch (v.precision) {
+        case MLMC_FP64: return launch_level_f64(v, p, grid, block, s);
+        case MLMC_FP32: return launch_level_f32(v, p, grid, block, s);
+        default: return launch_level_f16(v, p, grid, block, s);
+    }
+}
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(MLMC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- host tables (binary64 masters of the two dyadic approximations) ------------------
+struct HostTables {
+    double pwl[16][4];
+    double cubic[16][4];
+    bool ok = false;
+    HostTables() { ok = build_l2_table(1, pwl) && build_l2_table(3, cubic); }
+};
+
+const HostTables& host_tables() {
+    static const HostTables t;
+    return t;
+}
+
+int degree_of(int rv) { return rv == MLMC_RV_CUBIC16 ? 3 : 1; }
+
+// binary64 -> binary16 with one correctly rounded conversion (round to nearest even)
+__half half_of(double d) {
+    const _Float16 f = (_Float16)d;
+    __half h;
+    std::memcpy(&h, &f, sizeof h);
+    return h;
+}
+
+// ---- per-device state -------------------------------------------------------------------
+struct DevState {
+    bool ready = false;
+    int n_cu = 256;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    void* tables[2][3] = {{nullptr}};  // [pwl, cubic][precision], 16 x (d+1) coefficients
+    double* tables64[2] = {nullptr, nullptr};
+    double* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    double* out8 = nullptr;             // result slot of the synchronous entry point
+    __half* mlp = nullptr;              // MlpImage
+    bool mlp_loaded = false;
+};
+
+std::mutex g_mutex;
+std::map<int, DevState> g_devs;
+
+int current_device(int* dev) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(MLMC_ENODEV, "no HIP device available");
+    }
+    e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    return MLMC_OK;
+}
+
+int upload_tables(DevState& st) {
+    const HostTables& ht = host_tables();
+    if (!ht.ok) return fail(MLMC_EHIP, "dyadic table construction failed");
+    for (int r = 0; r < 2; ++r) {
+        const double(*src)[4] = r == 0 ? ht.pwl : ht.cubic;
+        const int d = r == 0 ? 1 : 3;
+        const int n = 16 * (d + 1);
+        double h64[64];
+        float h32[64];
+        __half h16[64];
+        for (int j = 0; j < 16; ++j)
+            for (int i = 0; i <= d; ++i) {
+                const double c = src[j][i];
+                h64[j * (d + 1) + i] = c;
+                h32[j * (d + 1) + i] = (float)c;
+                h16[j * (d + 1) + i] = half_of(c);  // one rounding from binary64
+            }
+        hipError_t e;
+        if ((e = hipMalloc(&st.tables[r][MLMC_FP64], n * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&st.tables[r][MLMC_FP32], n * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&st.tables[r][MLMC_FP16], n * sizeof(__half))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMemcpy(st.tables[r][MLMC_FP64], h64, n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(st.tables[r][MLMC_FP32], h32, n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(st.tables[r][MLMC_FP16], h16, n * sizeof(__half), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "hipMemcpy");
+        st.tables64[r] = (double*)st.tables[r][MLMC_FP64];
+    }
+    return MLMC_OK;
+}
+
+// Returns the initialised state of the current device (lazily created).
+int device_state(DevState** out) {
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    DevState& st = g_devs[dev];
+    if (!st.ready) {
+        hipDeviceProp_t prop;
+        hipError_t e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(MLMC_ENODEV, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+        st.n_cu = prop.multiProcessorCount;
+        if ((e = hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
+        if ((e = hipEventCreate(&st.ev0)) != hipSuccess || (e = hipEventCreate(&st.ev1)) != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+        if ((e = hipMalloc(&st.out8, kPartial * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&st.mlp, sizeof(MlpImage))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        rc = upload_tables(st);
+        if (rc) return rc;
+        st.ready = true;
+    }
+    *out = &st;
+    return MLMC_OK;
+}
+
+int ensure_scratch(DevState& st, size_t bytes) {
+    if (bytes <= st.scratch_bytes) return MLMC_OK;
+    if (st.scratch) {
+        hipError_t e = hipStreamSynchronize(st.stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(st.scratch);
+        st.scratch = nullptr;
+        st.scratch_bytes = 0;
+    }
+    size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    hipError_t e = hipMalloc(&st.scratch, want);
+    if (e != hipSuccess) return fail(MLMC_ENOMEM, "hipMalloc of %zu scratch bytes failed", want);
+    st.scratch_bytes = want;
+    return MLMC_OK;
+}
+
+// ---- argument validation (no HIP calls) ---------------------------------------------------
+bool finite(double v) { return std::isfinite(v); }
+
+int validate_sde(const mlmc_gbm_t* s) {
+    if (!s) return fail(MLMC_EINVAL, "sde is NULL");
+    if (!finite(s->mu) || !finite(s->sigma) || !finite(s->x0) || !finite(s->T) || !finite(s->strike))
+        return fail(MLMC_EINVAL, "sde has a non-finite field");
+    if (!(s->T > 0)) return fail(MLMC_EINVAL, "sde.T must be positive");
+    if (s->sigma < 0) return fail(MLMC_EINVAL, "sde.sigma must be non-negative");
+    if (s->payoff != MLMC_PAYOFF_X && s->payoff != MLMC_PAYOFF_CALL)
+        return fail(MLMC_EINVAL, "sde.payoff %d is not MLMC_PAYOFF_X or MLMC_PAYOFF_CALL", s->payoff);
+    return MLMC_OK;
+}
+
+int rv_of_mode(int rv_mode, int* rv, bool* nested) {
+    switch (rv_mode) {
+        case MLMC_EXACT: *rv = MLMC_RV_EXACT; *nested = false; return MLMC_OK;
+        case MLMC_APPROX_PWL16: *rv = MLMC_RV_PWL16; *nested = false; return MLMC_OK;
+        case MLMC_APPROX_CUBIC16: *rv = MLMC_RV_CUBIC16; *nested = false; return MLMC_OK;
+        case MLMC_APPROX_MLP: *rv = MLMC_RV_MLP; *nested = false; return MLMC_OK;
+        case MLMC_NESTED_PWL16: *rv = MLMC_RV_PWL16; *nested = true; return MLMC_OK;
+        case MLMC_NESTED_CUBIC16: *rv = MLMC_RV_CUBIC16; *nested = true; return MLMC_OK;
+        case MLMC_NESTED_MLP: *rv = MLMC_RV_MLP; *nested = true; return MLMC_OK;
+        default: return fail(MLMC_EINVAL, "rv_mode %d is not a valid MLMC_EXACT/APPROX/NESTED mode", rv_mode);
+    }
+}
+
+int validate_args(const mlmc_level_args_t* a, Variant* v) {
+    if (!a) return fail(MLMC_EINVAL, "args is NULL");
+    int rc = validate_sde(&a->sde);
+    if (rc) return rc;
+    if (a->level < 0 || a->level > kMaxLevel) return fail(MLMC_EINVAL, "level %d outside 0..%d", a->level, kMaxLevel);
+    if (a->precision < MLMC_FP64 || a->precision > MLMC_FP16)
+        return fail(MLMC_EINVAL, "precision %d is not MLMC_FP64/FP32/FP16", a->precision);
+    if (a->kahan != 0 && a->kahan != 1) return fail(MLMC_EINVAL, "kahan must be 0 or 1");
+    if (a->diag != 0 && a->diag != 1) return fail(MLMC_EINVAL, "diag must be 0 or 1");
+    if (a->stream > 0xFFFFu) return fail(MLMC_EINVAL, "stream %u exceeds 65535", a->stream);
+    const uint64_t lim = 1ull << 32;
+    if (a->n_paths > lim || a->path_offset > lim || a->path_offset + a->n_paths > lim)
+        return fail(MLMC_EINVAL, "path_offset + n_paths exceeds 2^32");
+    int rv;
+    bool nested;
+    rc = rv_of_mode(a->rv_mode, &rv, &nested);
+    if (rc) return rc;
+    if (rv == MLMC_RV_EXACT && a->precision != MLMC_FP64)
+        return fail(MLMC_EINVAL, "MLMC_EXACT (the plain estimator) runs in MLMC_FP64");
+    if (rv == MLMC_RV_EXACT && a->diag) return fail(MLMC_EINVAL, "diag needs an approximate rv_mode");
+    v->precision = a->precision;
+    v->rv = rv;
+    v->nested = nested;
+    v->kahan = a->kahan && a->precision != MLMC_FP64;
+    v->diag = a->diag != 0;
+    return MLMC_OK;
+}
+
+uint64_t n_chunks_of(const mlmc_level_args_t* a) {
+    const uint64_t cp = chunk_paths(a->precision);
+    return (a->n_paths + cp - 1) / cp;
+}
+
+LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevState& st, double* partials) {
+    LevelParams p;
+    std::memset(&p, 0, sizeof p);
+    const mlmc_gbm_t& s = a->sde;
+    // binary64 constants, then one rounding to each working precision
+    const double dt = s.T * std::ldexp(1.0, -a->level);
+    const double ca = s.mu * dt;
+    const double cac = s.mu * (2.0 * dt);
+    const double cb = s.sigma * std::sqrt(dt);
+    p.ca_f64 = ca; p.cac_f64 = cac; p.cb_f64 = cb; p.x0_f64 = s.x0; p.k_f64 = s.strike;
+    p.ca_f32 = (float)ca; p.cac_f32 = (float)cac; p.cb_f32 = (float)cb; p.x0_f32 = (float)s.x0; p.k_f32 = (float)s.strike;
+    p.ca_f16 = half_of(ca); p.cac_f16 = half_of(cac); p.cb_f16 = half_of(cb);
+    p.x0_f16 = half_of(s.x0); p.k_f16 = half_of(s.strike);
+    p.payoff = s.payoff;
+    p.level = a->level;
+    p.n_steps = 1u << a->level;
+    p.n_paths = a->n_paths;
+    p.path_offset = a->path_offset;
+    p.key0 = (uint32_t)a->seed;
+    p.key1 = (uint32_t)(a->seed >> 32);
+    p.ctr2 = (a->stream << 16) | (uint32_t)a->level;
+    p.pset = a->pset;
+    if (v.rv == MLMC_RV_PWL16 || v.rv == MLMC_RV_CUBIC16) {
+        const int r = v.rv == MLMC_RV_PWL16 ? 0 : 1;
+        p.table = st.tables[r][v.precision];
+        p.table64 = st.tables64[r];
+    }
+    p.mlp = st.mlp;
+    p.partials = partials;
+    return p;
+}
+
+void launch_shape(const DevState& st, uint64_t n_chunks, int* grid, int* block) {
+    const int waves_per_block = 4;
+    *block = waves_per_block * kWave;
+    const uint64_t max_blocks = (uint64_t)st.n_cu * 8;  // 32 resident waves per CU
+    uint64_t blocks = (n_chunks + waves_per_block - 1) / waves_per_block;
+    if (blocks > max_blocks) blocks = max_blocks;
+    if (blocks == 0) blocks = 1;
+    *grid = (int)blocks;
+}
+
+// Enqueue level + reduction on `s`; result (8 doubles) to d_out.
+int enqueue_level(DevState& st, const mlmc_level_args_t* a, const Variant& v, double* d_out, double* partials,
+                  double* out_pf_hat, double* out_pc_hat, double* out_pf_bar, double* out_pc_bar,
+                  double* out_xf_tilde, hipStream_t s) {
+    if (v.rv == MLMC_RV_MLP && !st.mlp_loaded)
+        return fail(MLMC_EUNSUPPORTED, "MLMC_RV_MLP needs weights: call mlmc_mlp_load first");
+    const uint64_t n_chunks = n_chunks_of(a);
+    LevelParams p = make_params(a, v, st, partials);
+    p.out_pf_hat = out_pf_hat;
+    p.out_pc_hat = out_pc_hat;
+    p.out_pf_bar = out_pf_bar;
+    p.out_pc_bar = out_pc_bar;
+    p.out_xf_tilde = out_xf_tilde;
+    hipError_t e;
+    if (n_chunks > 0) {
+        int grid, block;
+        launch_shape(st, n_chunks, &grid, &block);
+        e = launch_level(v, p, grid, block, s);
+        if (e != hipSuccess) return hip_fail(e, "level kernel launch");
+    }
+    if (d_out) {
+        e = launch_reduce(partials, n_chunks, d_out, s);
+        if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
+    }
+    return MLMC_OK;
+}
+
+void term_mask(const Variant& v, bool m[4]) {
+    m[MLMC_TERM_TWO_WAY] = true;
+    m[MLMC_TERM_FOUR_WAY] = v.nested;
+    m[MLMC_TERM_TWO_WAY_EXACT] = v.nested;
+    m[MLMC_TERM_ROUNDING] = v.diag;
+}
+
+}  // namespace
+}  // namespace mlmc
+
+using namespace mlmc;
+
+extern "C" {
+
+int mlmc_init(int device) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(MLMC_ENODEV, "no HIP device available");
+    }
+    if (device < 0 || device >= n) return fail(MLMC_EINVAL, "device %d outside 0..%d", device, n - 1);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    DevState* st;
+    return device_state(&st);
+}
+
+int mlmc_shutdown(void) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_devs) {
+        DevState& st = kv.second;
+        if (hipSetDevice(kv.first) != hipSuccess) continue;
+        (void)hipDeviceSynchronize();
+        for (auto& row : st.tables)
+            for (void*& t : row)
+                if (t) (void)hipFree(t);
+        if (st.scratch) (void)hipFree(st.scratch);
+        if (st.out8) (void)hipFree(st.out8);
+        if (st.mlp) (void)hipFree(st.mlp);
+        if (st.ev0) (void)hipEventDestroy(st.ev0);
+        if (st.ev1) (void)hipEventDestroy(st.ev1);
+        if (st.stream) (void)hipStreamDestroy(st.stream);
+    }
+    g_devs.clear();
+    (void)hipSetDevice(cur);
+    return MLMC_OK;
+}
+
+const char* mlmc_last_error(void) { return g_error.c_str(); }
+
+size_t mlmc_level_workspace_bytes(const mlmc_level_args_t* args) {
+    Variant v;
+    if (validate_args(args, &v)) return 0;
+    const uint64_t n = n_chunks_of(args);
+    return (size_t)(n == 0 ? 1 : n) * kPartial * sizeof(double);
+}
+
+int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspace, size_t workspace_bytes,
+                  void* hip_stream) {
+    Variant v;
+    int rc = validate_args(args, &v);
+    if (rc) return rc;
+    if (!d_out) return fail(MLMC_EINVAL, "d_out is NULL");
+    const size_t need = (size_t)(n_chunks_of(args) == 0 ? 1 : n_chunks_of(args)) * kPartial * sizeof(double);
+    if (d_workspace && workspace_bytes < need)
+        return fail(MLMC_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+    DevState* st;
+    if ((rc = device_state(&st))) return rc;
+    double* partials = (double*)d_workspace;
+    if (!partials) {
+        if ((rc = ensure_scratch(*st, need))) return rc;
+        partials = st->scratch;
+    }
+    return enqueue_level(*st, args, v, d_out, partials, nullptr, nullptr, nullptr, nullptr, nullptr,
+                         (hipStream_t)hip_stream);
+}
+
+int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision, int rv_mode, int kahan,
+               uint64_t seed, mlmc_result_t* out) {
+    if (!sde) return fail(MLMC_EINVAL, "sde is NULL");
+    if (!out) return fail(MLMC_EINVAL, "out is NULL");
+    mlmc_level_args_t a;
+    std::memset(&a, 0, sizeof a);
+    a.sde = *sde;
+    a.level = level;
+    a.precision = precision;
+    a.rv_mode = rv_mode;
+    a.kahan = kahan;
+    a.diag = 0;
+    a.stream = rv_mode >= MLMC_NESTED_PWL16 ? 1u : 0u;
+    a.pset = 0;
+    a.seed = seed;
+    a.n_paths = n_paths;
+    a.path_offset = 0;
+    Variant v;
+    int rc = validate_args(&a, &v);
+    if (rc) return rc;
+    DevState* st;
+    if ((rc = device_state(&st))) return rc;
+    const size_t need = (size_t)(n_chunks_of(&a) == 0 ? 1 : n_chunks_of(&a)) * kPartial * sizeof(double);
+    if ((rc = ensure_scratch(*st, need))) return rc;
+    hipError_t e = hipEventRecord(st->ev0, st->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    rc = enqueue_level(*st, &a, v, st->out8, st->scratch, nullptr, nullptr, nullptr, nullptr, nullptr, st->stream);
+    if (rc) return rc;
+    if ((e = hipEventRecord(st->ev1, st->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    double h[kPartial];
+    if ((e = hipMemcpyAsync(h, st->out8, sizeof h, hipMemcpyDeviceToHost, st->stream)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(st->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, st->ev0, st->ev1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    bool m[4];
+    term_mask(v, m);
+    for (int k = 0; k < kTerms; ++k) {
+        out->sum[k] = m[k] ? h[k] : NAN;
+        out->sumsq[k] = m[k] ? h[kTerms + k] : NAN;
+    }
+    out->n_paths = n_paths;
+    out->path_steps = n_paths << level;
+    out->cost_seconds = 1e-3 * (double)ms;
+    return MLMC_OK;
+}
+
+int mlmc_paths(const mlmc_level_args_t* args, double* d_pf_hat, double* d_pc_hat, double* d_pf_bar,
+               double* d_pc_bar, double* d_xf_tilde, void* hip_stream) {
+    Variant v;
+    int rc = validate_args(args, &v);
+    if (rc) return rc;
+    DevState* st;
+    if ((rc = device_state(&st))) return rc;
+    const size_t need = (size_t)(n_chunks_of(args) == 0 ? 1 : n_chunks_of(args)) * kPartial * sizeof(double);
+    if ((rc = ensure_scratch(*st, need))) return rc;
+    return enqueue_level(*st, args, v, nullptr, st->scratch, d_pf_hat, d_pc_hat, d_pf_bar, d_pc_bar, d_xf_tilde,
+                         (hipStream_t)hip_stream);
+}
+
+int mlmc_uniforms(uint64_t seed, uint32_t stream, int level, uint32_t pset, uint64_t path0, uint64_t n_paths,
+                  uint32_t n_steps, uint32_t* d_words, void* hip_stream) {
+    if (!d_words && n_paths > 0 && n_steps > 0) return fail(MLMC_EINVAL, "d_words is NULL");
+    if (stream > 0xFFFFu) return fail(MLMC_EINVAL, "stream %u exceeds 65535", stream);
+    if (level < 0 || level > 0xFFFF) return fail(MLMC_EINVAL, "level %d outside 0..65535", level);
+    if (n_steps > (1u << kMaxLevel)) return fail(MLMC_EINVAL, "n_steps exceeds 2^%d", kMaxLevel);
+    if (path0 + n_paths > (1ull << 32)) return fail(MLMC_EINVAL, "path0 + n_paths exceeds 2^32");
+    DevState* st;
+    int rc = device_state(&st);
+    if (rc) return rc;
+    if (n_paths == 0 || n_steps == 0) return MLMC_OK;
+    hipError_t e = launch_uniforms(seed, (stream << 16) | (uint32_t)level, pset, path0, n_paths, n_steps, d_words,
+                                   (hipStream_t)hip_stream);
+    return e == hipSuccess ? MLMC_OK : hip_fail(e, "uniforms kernel launch");
+}
+
+int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double* d_out, void* hip_stream) {
+    if ((!d_words || !d_out) && n > 0) return fail(MLMC_EINVAL, "NULL buffer");
+    if (rv < MLMC_RV_EXACT || rv > MLMC_RV_MLP) return fail(MLMC_EINVAL, "rv %d is not an MLMC_RV_* kind", rv);
+    if (precision < MLMC_FP64 || precision > MLMC_FP16) return fail(MLMC_EINVAL, "precision %d invalid", precision);
+    DevState* st;
+    int rc = device_state(&st);
+    if (rc) return rc;
+    if (rv == MLMC_RV_MLP && !st->mlp_loaded)
+        return fail(MLMC_EUNSUPPORTED, "MLMC_RV_MLP needs weights: call mlmc_mlp_load first");
+    if (n == 0) return MLMC_OK;
+    const void* table = nullptr;
+    if (rv == MLMC_RV_PWL16 || rv == MLMC_RV_CUBIC16) table = st->tables[rv == MLMC_RV_PWL16 ? 0 : 1][precision];
+    hipError_t e = launch_icdf(d_words, n, rv, precision, table, st->mlp, d_out, (hipStream_t)hip_stream);
+    return e == hipSuccess ? MLMC_OK : hip_fail(e, "icdf kernel launch");
+}
+
+int mlmc_table(int rv, int precision, double* h_out) {
+    if (!h_out) return fail(MLMC_EINVAL, "h_out is NULL");
+    if (rv != MLMC_RV_PWL16 && rv != MLMC_RV_CUBIC16) return fail(MLMC_EINVAL, "rv must be PWL16 or CUBIC16");
+    if (precision < MLMC_FP64 || precision > MLMC_FP16) return fail(MLMC_EINVAL, "precision %d invalid", precision);
+    const HostTables& ht = host_tables();
+    if (!ht.ok) return fail(MLMC_EHIP, "dyadic table construction failed");
+    const double(*src)[4] = rv == MLMC_RV_PWL16 ? ht.pwl : ht.cubic;
+    const int d = degree_of(rv);
+    for (int j = 0; j < 16; ++j)
+        for (int i = 0; i < 4; ++i) {
+            const double c = i <= d ? src[j][i] : 0.0;
+            double r = c;
+            if (precision == MLMC_FP32) r = (double)(float)c;
+            if (precision == MLMC_FP16) r = (double)__half2float(half_of(c));
+            h_out[j * 4 + i] = r;
+        }
+    return MLMC_OK;
+}
+
+}  // extern "C"

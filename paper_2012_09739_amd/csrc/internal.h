@@ -1,0 +1,68 @@
+// Internal definitions shared by the host library and its kernels (not part of the C-ABI).
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mlmc.h"
+
+namespace mlmc {
+
+constexpr int kTerms = 4;           // two-way, four-way, two-way exact part, rounding diagnostic
+constexpr int kPartial = 2 * kTerms;  // (sum, sum of squares) per term
+constexpr int kWave = 64;
+constexpr int kMaxLevel = 24;
+constexpr int kTableRows = 16;
+
+// Per-launch parameters of one MLMC level (one parameter set).  Constants are rounded
+// on the host from binary64, once, to the working precision p (R_p(mu delta) etc.).
+struct LevelParams {
+    // exact pair (binary64)
+    double ca_f64, cac_f64, cb_f64, x0_f64, k_f64;
+    // approximate pair in binary32 (also used for the binary64 approximate pair via *_f64)
+    float ca_f32, cac_f32, cb_f32, x0_f32, k_f32;
+    // approximate pair in binary16
+    __half ca_f16, cac_f16, cb_f16, x0_f16, k_f16;
+    int payoff;
+    int level;
+    uint32_t n_steps;
+    uint64_t n_paths;      // paths in this launch
+    uint64_t path_offset;  // first global path index (Philox counter word 1)
+    uint32_t key0, key1;   // seed
+    uint32_t ctr2;         // (stream << 16) | level
+    uint32_t pset;
+    const void* table;     // 16 x (DEG + 1) coefficients in the working precision
+    const double* table64; // 16 x (DEG + 1) binary64 master coefficients (diagnostic)
+    const void* mlp;       // MLP inference image (rv = MLP)
+    double* partials;      // [n_chunks][kPartial] chunk partial sums
+    // optional per-path outputs (device, n_paths entries each, may be null)
+    double* out_pf_hat;
+    double* out_pc_hat;
+    double* out_pf_bar;
+    double* out_pc_bar;
+    double* out_xf_tilde;
+};
+
+// Template variant selector.
+struct Variant {
+    int precision;  // MLMC_FP64 / MLMC_FP32 / MLMC_FP16
+    int rv;         // MLMC_RV_EXACT / PWL16 / CUBIC16 / MLP
+    bool nested;
+    bool kahan;
+    bool diag;
+};
+
+// Launch helpers implemented in the .hip translation units.
+hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* d_out, hipStream_t s);
+hipError_t launch_uniforms(uint64_t seed, uint32_t ctr2, uint32_t pset, uint64_t path0,
+                           uint64_t n_paths, uint32_t n_steps, uint32_t* d_words, hipStream_t s);
+hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, const void* table,
+                       const void* mlp, double* d_out, hipStream_t s);
+
+// Paths covered by one wave-chunk (the unit of the fixed-order reduction).
+inline uint32_t chunk_paths(int precision) { return precision == MLMC_FP16 ? 2 * kWave : kWave; }
+
+}  // namespace mlmc

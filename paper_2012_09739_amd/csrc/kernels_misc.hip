@@ -1,0 +1,128 @@
+// Chunk-partial reduction and the parity-check kernels (uniform words, inverse CDF values).
+#include <hip/hip_runtime.h>
+
+#include "icdf.h"
+#include "internal.h"
+#include "mlp.h"
+#include "philox.h"
+
+namespace mlmc {
+
+namespace {
+
+constexpr int kReduceBlock = 256;
+
+// Sums the [n_chunks][8] chunk partials in a fixed order: thread t accumulates chunks
+// t, t + 256, ... sequentially, then a fixed tree over the 256 threads.  The order
+// depends only on n_chunks, so results do not depend on the level kernel's launch shape.
+__global__ __launch_bounds__(kReduceBlock) void reduce_chunks(const double* __restrict__ partials,
+                                                              uint64_t n_chunks, double* __restrict__ out) {
+    __shared__ double s[kPartial][kReduceBlock];
+    double acc[kPartial];
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
+    for (uint64_t c = threadIdx.x; c < n_chunks; c += kReduceBlock) {
+#pragma unroll
+        for (int k = 0; k < kPartial; ++k) acc[k] += partials[c * kPartial + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = kReduceBlock / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < kPartial; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kPartial) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void uniforms_kernel(uint32_t k0, uint32_t k1, uint32_t ctr2, uint32_t pset, uint64_t path0,
+                                uint64_t n_paths, uint32_t n_steps, uint32_t* __restrict__ words) {
+    const uint64_t n_calls = (n_steps + 3) / 4;
+    const uint64_t total = n_paths * n_calls;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = g / n_calls;
+        const uint32_t q = (uint32_t)(g % n_calls);
+        const Words4 r = philox4x32_10(q, (uint32_t)(path0 + p), ctr2, pset, k0, k1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t n = 4 * q + i;
+            if (n < n_steps) words[p * n_steps + n] = r.w[i];
+        }
+    }
+}
+
+template <int RV, int PREC>
+__global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, const void* table,
+                            const void* mlp, double* __restrict__ out) {
+    constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = words[g];
+        double z;
+        if constexpr (RV == MLMC_RV_EXACT) {
+            z = icdf_exact_f64(w);
+        } else if constexpr (RV == MLMC_RV_MLP) {
+            const float y = icdf_mlp_f32(w, (const __half*)mlp);
+            if constexpr (PREC == MLMC_FP16) z = (double)__half2float(__float2half_rn(y));
+            else z = (double)y;
+        } else if constexpr (PREC == MLMC_FP64) {
+            z = icdf_dyadic_f64<DEG>(w, (const double*)table);
+        } else if constexpr (PREC == MLMC_FP32) {
+            z = (double)icdf_dyadic_f32<DEG>(w, (const float*)table);
+        } else {
+            z = (double)__half2float(icdf_dyadic_f16<DEG>(w, (const __half*)table));
+        }
+        out[g] = z;
+    }
+}
+
+int grid_for(uint64_t n, int block) {
+    const uint64_t g = (n + block - 1) / block;
+    return (int)(g < 65536 ? (g == 0 ? 1 : g) : 65536);
+}
+
+}  // namespace
+
+hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* d_out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_chunks, dim3(1), dim3(kReduceBlock), 0, s, partials, n_chunks, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniforms(uint64_t seed, uint32_t ctr2, uint32_t pset, uint64_t path0, uint64_t n_paths,
+                           uint32_t n_steps, uint32_t* d_words, hipStream_t s) {
+    const uint64_t total = n_paths * ((n_steps + 3) / 4);
+    hipLaunchKernelGGL(uniforms_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), ctr2, pset, path0, n_paths, n_steps, d_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, const void* table,
+                       const void* mlp, double* d_out, hipStream_t s) {
+    const dim3 g(grid_for(n, 256)), b(256);
+#define MLMC_ICDF_CASE(R, P) \
+    if (rv == R && precision == P) { \
+        hipLaunchKernelGGL((icdf_kernel<R, P>), g, b, 0, s, d_words, n, table, mlp, d_out); \
+        return hipGetLastError(); \
+    }
+    if (rv == MLMC_RV_EXACT) {
+        hipLaunchKernelGGL((icdf_kernel<MLMC_RV_EXACT, MLMC_FP64>), g, b, 0, s, d_words, n, table, mlp, d_out);
+        return hipGetLastError();
+    }
+    MLMC_ICDF_CASE(MLMC_RV_PWL16, MLMC_FP64)
+    MLMC_ICDF_CASE(MLMC_RV_PWL16, MLMC_FP32)
+    MLMC_ICDF_CASE(MLMC_RV_PWL16, MLMC_FP16)
+    MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_FP64)
+    MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_FP32)
+    MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_FP16)
+    MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP64)
+    MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP32)
+    MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP16)
+#undef MLMC_ICDF_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mlmc

@@ -1,0 +1,99 @@
+"""CPU tests of the C-ABI library: it loads, exports every entry point include/mlmc.h
+declares, validates arguments before touching HIP, reports ENODEV without a GPU, and its
+host-built coefficient tables agree with the oracle's (an independent construction)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2012_09739_amd as M
+from oracle import tables
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mlmc.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(mlmc_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for n in ("mlmc_level", "mlmc_level_ex", "mlmc_paths", "mlmc_uniforms", "mlmc_icdf", "mlmc_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(M.mlmc.LIB_PATH)
+    for name in declared():
+        assert hasattr(lib, name), name
+    assert set(declared()) <= set(M.exported_symbols())
+
+
+def _gpu_visible():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(level=-1), M.MLMC_EINVAL), (dict(level=25), M.MLMC_EINVAL), (dict(precision=3), M.MLMC_EINVAL),
+    (dict(rv_mode=4), M.MLMC_EINVAL), (dict(rv_mode=8), M.MLMC_EINVAL), (dict(kahan=2), M.MLMC_EINVAL),
+    (dict(precision=M.MLMC_FP32, rv_mode=M.MLMC_EXACT), M.MLMC_EINVAL), (dict(n_paths=2 ** 32 + 1), M.MLMC_EINVAL)])
+def test_invalid_arguments(kw, code):
+    a = dict(level=3, n_paths=10, precision=M.MLMC_FP64, rv_mode=M.MLMC_EXACT, kahan=0)
+    a.update(kw)
+    with pytest.raises(M.MlmcError) as e:
+        M.mlmc_level(M.gbm(), a["level"], a["n_paths"], a["precision"], a["rv_mode"], a["kahan"], 0)
+    assert e.value.code == code
+    assert M.mlmc_last_error()
+
+
+@pytest.mark.parametrize("sde", [M.gbm(T=0.0), M.gbm(sigma=-1.0), M.gbm(payoff=7), M.gbm(mu=float("nan"))])
+def test_invalid_sde(sde):
+    with pytest.raises(M.MlmcError) as e:
+        M.mlmc_level(sde, 3, 10, M.MLMC_FP64, M.MLMC_EXACT, 0, 0)
+    assert e.value.code == M.MLMC_EINVAL
+
+
+def test_null_pointers_rejected():
+    lib = M.lib()
+    r = M.mlmc_result_t()
+    assert lib.mlmc_level(None, 1, 1, 0, 0, 0, 0, ctypes.byref(r)) == M.MLMC_EINVAL
+    s = M.gbm()
+    assert lib.mlmc_level(ctypes.byref(s), 1, 1, 0, 0, 0, 0, None) == M.MLMC_EINVAL
+    args = M.level_args(s, 2, 10, 0, 0)
+    assert lib.mlmc_level_ex(ctypes.byref(args), None, None, 0, None) == M.MLMC_EINVAL
+    assert lib.mlmc_level_ex(None, None, None, 0, None) == M.MLMC_EINVAL
+    assert lib.mlmc_table(1, 0, None) == M.MLMC_EINVAL
+    assert lib.mlmc_level_workspace_bytes(None) == 0
+
+
+def test_workspace_size():
+    args = M.level_args(M.gbm(), 5, 1000, M.MLMC_FP32, M.MLMC_NESTED_PWL16)
+    assert M.mlmc_level_workspace_bytes(args) == 16 * 8 * 8     # 16 chunks of 64 paths
+    args16 = M.level_args(M.gbm(), 5, 1000, M.MLMC_FP16, M.MLMC_NESTED_PWL16)
+    assert M.mlmc_level_workspace_bytes(args16) == 8 * 8 * 8    # 8 chunks of 128 paths
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="a GPU is visible")
+def test_no_device_is_reported():
+    with pytest.raises(M.MlmcError) as e:
+        M.mlmc_level(M.gbm(), 3, 10, M.MLMC_FP64, M.MLMC_EXACT, 0, 0)
+    assert e.value.code == M.MLMC_ENODEV
+
+
+@pytest.mark.parametrize("rv,deg", [(M.MLMC_RV_PWL16, 1), (M.MLMC_RV_CUBIC16, 3)])
+def test_library_table_matches_oracle_table(rv, deg):
+    want = np.array(tables.table(deg))
+    got = np.array(M.mlmc_table(rv, M.MLMC_FP64))
+    assert np.all(got[:, deg + 1:] == 0)
+    got = got[:, :deg + 1]
+    assert np.max(np.abs(got - want) / np.abs(want)) < 1e-12
+    for p, dt in ((M.MLMC_FP32, np.float32), (M.MLMC_FP16, np.float16)):
+        np.testing.assert_array_equal(np.array(M.mlmc_table(rv, p))[:, :deg + 1], want.astype(dt).astype(np.float64))
