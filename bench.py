@@ -1,0 +1,211 @@
+"""Benchmark: nested four-way MLMC in binary32 on one MI355X.
+
+Workload (one "step" = one pass of the whole hot path over one batch of synthetic input):
+geometric Brownian motion mu = 0.05, sigma = 0.2, X0 = 1, T = 1, European call
+max(X_T - 1, 0); nested four-way samples (exact binary64 pair and approximate binary32
+pair from the same Philox4x32-10 uniforms, piecewise-linear inverse CDF on 16 dyadic
+intervals) at levels 0..10 with 2^20 paths per level, once without and once with Kahan
+compensation.  Each sample yields the four-way difference and both two-way differences
+with on-device binary64 sums and sums of squares.
+
+Metric: coupled path-steps per second (one coupled path-step = one fine time step of one
+coupled sample, including its share of the coarse step) -- inputs are seeds, resident on
+the device by construction.  Besides the headline number the JSON line reports the plain
+binary64 estimator's throughput at the same sizes and the speed-up of the nested
+binary32 estimator over it at equal total MLMC variance (T^ / T-, from measured
+per-level variances and device costs), the roofline of the dominant kernel and the CPU
+oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LEVELS = list(range(11))
+N_PATHS = 2 ** 20
+SEED = 0
+# VALU peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz, one full-rate VALU lane-operation
+# per lane per clock (= the binary64 vector peak 78.6 TFLOP/s / 2 flops per FMA)
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic VALU lane-operations per coupled path-step of the nested binary32
+# piecewise-linear kernel with Kahan updates (operation list in the design doc)
+ALG_OPS_PER_STEP = 107.5
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-speedup", action="store_true", help="skip the equal-variance legs")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a device copy of known size (HBM counter calibration)")
+    return p.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU kernel; "
+              "paths shard across GPUs by path_offset (see DESIGN.md) but no multi-GPU run is made",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2012_09739_amd as M
+    from paper_2012_09739_amd import estimators as E
+
+    torch.cuda.set_device(0)
+    M.mlmc_init(0)
+    stream = torch.cuda.current_stream()
+    call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
+    args = {k: [M.level_args(call, l, N_PATHS, M.MLMC_FP32, M.MLMC_NESTED_PWL16, k, SEED) for l in LEVELS]
+            for k in (0, 1)}
+    out = torch.zeros((2, len(LEVELS), 8), dtype=torch.float64, device="cuda")
+    ws_bytes = max(M.mlmc_level_workspace_bytes(x) for x in args[0])
+    ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device="cuda")
+    top = LEVELS[-1]
+    ev = []   # (start, end) events around the dominant kernel: level 10, Kahan
+
+    def step(record):
+        for k in (0, 1):
+            for i, l in enumerate(LEVELS):
+                timed = record and k == 1 and l == top
+                if timed:
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                M.mlmc_level_ex(args[k][i], out[k, i], ws, ws_bytes, stream)
+                if timed:
+                    e1.record(stream)
+                    ev.append((e0, e1))
+
+    for _ in range(a.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    steps_per_pass = 2 * N_PATHS * sum(2 ** l for l in LEVELS)
+    seconds = t1 - t0
+    value = a.steps * steps_per_pass / seconds
+    kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
+    achieved = ALG_OPS_PER_STEP * N_PATHS * 2 ** top / (kern_ms * 1e-3) / 1e12
+    sums = out.cpu().numpy()
+    assert all(math.isfinite(v) for v in sums.ravel()), "non-finite level sums"
+
+    extra = {}
+    if not a.no_speedup:
+        extra = equal_variance_report(M, E, call)
+
+    if a.calibrate_copy:
+        src = torch.empty(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        extra["copy_calibration_bytes"] = 2 * src.numel() * 4
+
+    cpu = None if a.no_cpu_baseline else cpu_baseline()
+
+    line = {
+        "metric": "coupled path-steps/s FP16/FP32 vs FP64 at equal MLMC variance; % VALU peak",
+        "value": value,
+        "unit": "coupled path-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": seconds / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded Philox4x32-10 uniforms; no dataset)",
+        "config": {"workload": "nested four-way MLMC, GBM mu=0.05 sigma=0.2 X0=1 T=1, call K=1, "
+                               "binary32 approximate pair with piecewise-linear inverse CDF on 16 dyadic "
+                               "intervals, binary64 exact pair, levels 0..10, 2^20 paths/level, "
+                               "Kahan off and on",
+                   "levels": LEVELS, "paths_per_level": N_PATHS, "kahan": [0, 1],
+                   "coupled_path_steps_per_step": steps_per_pass, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+                     "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+                     "kernel": "level_kernel<FP32, PWL16, nested, kahan> at level 10 (2^20 paths x 1024 steps)",
+                     "kernel_ms": kern_ms, "alg_ops_per_path_step": ALG_OPS_PER_STEP},
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def equal_variance_report(M, E, call):
+    """Plain binary64 estimator vs nested binary32 at equal total MLMC variance (Section 3).
+
+    v^_l, c^_l: two-way exact differences in binary64 (the plain estimator's samples);
+    v-_l, c-_l: approximate two-way differences in binary32 (independent Philox stream 0);
+    V-_l, C-_l: four-way differences (nested samples, stream 1); costs are device times
+    per sample from the library's HIP events."""
+    rep = {}
+    res = {}
+    for name, prec, mode, k in (("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0),
+                                ("approx_fp32", M.MLMC_FP32, M.MLMC_APPROX_PWL16, 0),
+                                ("approx_fp32_kahan", M.MLMC_FP32, M.MLMC_APPROX_PWL16, 1),
+                                ("nested_fp32", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0),
+                                ("nested_fp32_kahan", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1)):
+        sde = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
+        rows = []
+        for l in LEVELS:
+            M.mlmc_level(sde, l, N_PATHS, prec, mode, k, SEED)  # warm
+            r = M.mlmc_level(sde, l, N_PATHS, prec, mode, k, SEED)
+            rows.append(r)
+        res[name] = rows
+    cost = lambda rows: [r["cost_seconds"] / r["n_paths"] for r in rows]  # noqa: E731
+    var = lambda rows, t: [E.level_stats(r["sum"][t], r["sumsq"][t], r["n_paths"])[1] for r in rows]  # noqa: E731
+    v_hat, c_hat = var(res["plain_fp64"], 0), cost(res["plain_fp64"])
+    steps = N_PATHS * sum(2 ** l for l in LEVELS)
+    rep["fp64_plain_path_steps_per_s"] = steps / sum(r["cost_seconds"] for r in res["plain_fp64"])
+    rep["equal_variance"] = {}
+    for tag, ap, ne in (("fp32", "approx_fp32", "nested_fp32"), ("fp32_kahan", "approx_fp32_kahan",
+                                                                "nested_fp32_kahan")):
+        v_bar, c_bar = var(res[ap], 0), cost(res[ap])
+        V_bar, C_bar = var(res[ne], 1), cost(res[ne])
+        rep["equal_variance"][tag] = {
+            "speedup_T_hat_over_T_bar": E.speedup_equal_variance(v_hat, c_hat, v_bar, c_bar, V_bar, C_bar),
+            "per_level_speedup": [1.0 / f for f in E.per_level_factor(v_hat, c_hat, v_bar, c_bar, V_bar, C_bar)],
+            "approx_two_way_path_steps_per_s": steps / sum(r["cost_seconds"] for r in res[ap]),
+            "four_way_over_two_way_variance": [V / v for V, v in zip(V_bar, v_hat)],
+        }
+    return rep
+
+
+def cpu_baseline():
+    """The CPU oracle (float64 NumPy, one thread) on a bounded sample of the same workload:
+    Kahan variant, levels 0..10, 2^14 paths per level (1/128 of the GPU pass)."""
+    import numpy as np  # noqa: F401
+
+    import mlmc_workloads as W
+    from oracle import fp, mlmc
+    n = 2 ** 14
+    t0 = time.perf_counter()
+    steps = 0
+    for l in LEVELS:
+        mlmc.level_sums(l, n, W.GBM_CALL, rv_mode=mlmc.RV_PWL, precision=fp.FP32, nested=True, kahan=True,
+                        seed=SEED, stream=1)
+        steps += n * 2 ** l
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "coupled path-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "nested binary32 PWL16 with Kahan, levels 0..10, 2^14 paths/level (%d coupled "
+                      "path-steps, %.1f s), single-threaded NumPy" % (steps, dt)}
+
+
+if __name__ == "__main__":
+    main()

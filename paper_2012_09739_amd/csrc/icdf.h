@@ -21,22 +21,53 @@
 
 namespace mlmc {
 
-template <int N>
-__device__ __forceinline__ double horner_fma(const double (&c)[N], double v) {
-    double acc = c[N - 1];
+// -log(y) for normal 0 < y <= 1.  y = 2^e m with m in [1/sqrt2, sqrt2) (exact), then
+// log m = 2 atanh(s) = 2s + s^3 R(s^2) with s = (m - 1)/(m + 1), R a fitted polynomial;
+// the reciprocal of m + 1 is refined by two Newton steps from the hardware estimate.
+// Absolute error about 1e-16 plus one rounding of the result.
+__device__ __forceinline__ double neg_log_f64(double y) {
+    constexpr double kR[] = MLMC_LOG_COEFFS;
+    int e = __builtin_amdgcn_frexp_exp(y);
+    double m = __builtin_amdgcn_frexp_mant(y);  // [1/2, 1)
+    const bool low = m < 0.70710678118654752440;
+    m = low ? m + m : m;
+    e = low ? e - 1 : e;
+    const double f = m - 1.0;  // exact
+    const double d = m + 1.0;
+    double r = __builtin_amdgcn_rcp(d);
+    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+    const double sv = f * r;
+    const double z = sv * sv;
+    double acc = kR[MLMC_LOG_DEG];
 #pragma unroll
-    for (int i = N - 2; i >= 0; --i) acc = __builtin_fma(acc, v, c[i]);
+    for (int i = MLMC_LOG_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, z, kR[i]);
+    const double log_m = __builtin_fma(sv * z, acc, sv + sv);
+    const double ed = (double)e;
+    // ln 2 split so that e * kLn2Hi is exact for |e| < 2^11
+    constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;
+    constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
+    return -__builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, log_m));
+}
+
+// g(w) on the tail w > 6.25 (fewer than one word in a thousand): out of line so that its
+// coefficients are materialised only when a lane needs them.
+__device__ __noinline__ double icdf_tail_g(double w) {
+    constexpr double kTail[] = MLMC_ICDF_TAIL_COEFFS;
+    double acc = kTail[MLMC_ICDF_TAIL_DEG];
+    const double d = __builtin_sqrt(w) - MLMC_ICDF_MID2;
+#pragma unroll
+    for (int i = MLMC_ICDF_TAIL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, d, kTail[i]);
     return acc;
 }
 
-__host__ __device__ __forceinline__ double icdf_exact_f64(uint32_t word) {
+__device__ __forceinline__ double icdf_exact_f64(uint32_t word) {
     // x = 2u - 1 = (v + 1/2) 2^-31 with v = word - 2^31 (exact in binary64)
     const int32_t v = (int32_t)(word ^ 0x80000000u);
     const double x = __builtin_fma((double)v, 0x1p-31, 0x1p-32);
     const double y = (1.0 - x) * (1.0 + x);
-    const double w = -log(y);
+    const double w = neg_log_f64(y);
     constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
-    constexpr double kTail[] = MLMC_ICDF_TAIL_COEFFS;
     double g;
     if (w <= MLMC_ICDF_W1) {
         double acc = kCentral[MLMC_ICDF_CENTRAL_DEG];
@@ -45,13 +76,75 @@ __host__ __device__ __forceinline__ double icdf_exact_f64(uint32_t word) {
         for (int i = MLMC_ICDF_CENTRAL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, d, kCentral[i]);
         g = acc;
     } else {
-        double acc = kTail[MLMC_ICDF_TAIL_DEG];
-        const double d = sqrt(w) - MLMC_ICDF_MID2;
-#pragma unroll
-        for (int i = MLMC_ICDF_TAIL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, d, kTail[i]);
-        g = acc;
+        g = icdf_tail_g(w);
     }
     return x * g;
+}
+
+// Places a binary64 constant in an SGPR pair at its point of use.  The polynomial
+// coefficients are then scalar operands of v_fma_f64 (one instruction per Horner step)
+// instead of loop-invariant VGPR copies that cost a v_mov per step and occupancy.
+__device__ __forceinline__ double sgpr_const(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
+// Exact variables of four words at once: the four Horner chains share every
+// coefficient (one scalar materialisation per coefficient for four FMAs) and give the
+// scheduler four independent dependency chains.
+__device__ __forceinline__ void icdf_exact_f64x4(const uint32_t (&word)[4], double (&z)[4]) {
+    constexpr double kR[] = MLMC_LOG_COEFFS;
+    constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
+    double x[4], sv[4], zz[4], acc[4], ed[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int32_t v = (int32_t)(word[k] ^ 0x80000000u);
+        x[k] = __builtin_fma((double)v, 0x1p-31, 0x1p-32);
+        const double y = (1.0 - x[k]) * (1.0 + x[k]);
+        int e = __builtin_amdgcn_frexp_exp(y);
+        double m = __builtin_amdgcn_frexp_mant(y);
+        const bool low = m < 0.70710678118654752440;
+        m = low ? m + m : m;
+        e = low ? e - 1 : e;
+        ed[k] = (double)e;
+        const double f = m - 1.0;
+        const double d = m + 1.0;
+        double r = __builtin_amdgcn_rcp(d);
+        r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+        r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+        sv[k] = f * r;
+        zz[k] = sv[k] * sv[k];
+        acc[k] = kR[MLMC_LOG_DEG];
+    }
+#pragma unroll
+    for (int i = MLMC_LOG_DEG - 1; i >= 0; --i) {
+        const double c = sgpr_const(kR[i]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = __builtin_fma(acc[k], zz[k], c);
+    }
+    double w[4], d[4];
+    bool tail = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double log_m = __builtin_fma(sv[k] * zz[k], acc[k], sv[k] + sv[k]);
+        w[k] = -__builtin_fma(ed[k], 0x1.62e42fefa3800p-1, __builtin_fma(ed[k], 0x1.ef35793c76730p-45, log_m));
+        tail |= w[k] > MLMC_ICDF_W1;
+        d[k] = w[k] - MLMC_ICDF_MID1;
+        acc[k] = kCentral[MLMC_ICDF_CENTRAL_DEG];
+    }
+#pragma unroll
+    for (int i = MLMC_ICDF_CENTRAL_DEG - 1; i >= 0; --i) {
+        const double c = sgpr_const(kCentral[i]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = __builtin_fma(acc[k], d[k], c);
+    }
+    if (tail) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (w[k] > MLMC_ICDF_W1) acc[k] = icdf_tail_g(w[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z[k] = x[k] * acc[k];
 }
 
 // Interval j-1 (0-based row of the table), mirror flag and the local coordinate scaled to

@@ -160,6 +160,11 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
             Words4 r[L];
 #pragma unroll
             for (int l = 0; l < L; ++l) r[l] = philox4x32_10(q, path[l], prm.ctr2, prm.pset, prm.key0, prm.key1);
+            double zx[L][4];
+            if constexpr (kNeedExact) {
+#pragma unroll
+                for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l]);
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (4 * q + i >= prm.n_steps) break;  // only at levels 0 and 1
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
                 if constexpr (kNeedExact) {
 #pragma unroll
                     for (int l = 0; l < L; ++l) {
-                        const double z = icdf_exact_f64(r[l].w[i]);
+                        const double z = zx[l][i];
                         em_step<double>(Xfh[l], z, prm.ca_f64, prm.cb_f64);
                         if (coarse) em_step<double>(Xch[l], zh_prev[l] + z, prm.cac_f64, prm.cb_f64);
                         else zh_prev[l] = z;
