@@ -179,6 +179,103 @@ int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double
  * rv: MLMC_RV_PWL16 or MLMC_RV_CUBIC16.  Host-only: needs no GPU. */
 int mlmc_table(int rv, int precision, double* h_out);
 
+/* ---- batched sweep: many (parameter set, level) items in one persistent launch -------
+ * Not in the paper: a full MLMC sweep (Section 3: every level l = 0..L, here also many
+ * GBM parameter sets) as one launch.  Each item is a nested sample set (terms 0, 1, 2 as
+ * in mlmc_level) of one level of one GBM.  Work is split into tasks (chunk ranges of one
+ * item), ordered longest first and popped by each wavefront from a device work queue;
+ * per-item sums are reduced in the same fixed order as mlmc_level, so every item's result
+ * equals the corresponding single-level call bit for bit. */
+typedef struct {
+    mlmc_gbm_t sde;
+    int32_t level;      /* 0..24                                                        */
+    int32_t precision;  /* MLMC_FP16 or MLMC_FP32 (the approximate pair)                 */
+    int32_t kahan;      /* 0/1                                                          */
+    uint32_t pset;      /* parameter-set id (Philox counter word 3)                     */
+    uint32_t stream;    /* Philox stream id 0..65535                                    */
+    uint32_t reserved;
+    uint64_t n_paths;   /* 1..2^32                                                      */
+    uint64_t seed;      /* Philox key                                                   */
+} mlmc_item_t;
+
+/* launch shape of a batch (0 in a field selects the default or the autotuned value) */
+typedef struct {
+    int32_t waves_per_cu;    /* resident wavefronts per CU of the persistent grid: 4..32   */
+    int32_t task_steps;      /* fine steps per task at level 0 (tasks of level l hold      */
+                             /* max(1, task_steps >> l) chunks): 1..2^20                 */
+    int32_t priority_level;  /* tasks of level >= this run at raised wave priority; 25=off */
+    int32_t reserved;
+} mlmc_batch_cfg_t;
+
+typedef struct mlmc_batch mlmc_batch_t; /* opaque plan (device task list + captured graph) */
+
+/* Build a plan for n_items items (host array, copied) that all use approximation rv
+ * (MLMC_RV_PWL16 or MLMC_RV_CUBIC16).  d_out: device, n_items x 8 doubles (sum[0..3],
+ * sumsq[0..3] per item; term 3 is 0), owned by the caller and written by every run.  cfg:
+ * host, may be NULL (defaults, or the cached autotuned shape for this item list).  The
+ * launch sequence (queue reset, persistent kernel, per-item reduction) is captured into a
+ * hipGraph.  *out_plan receives the plan; free it with mlmc_batch_destroy. */
+int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_batch_cfg_t* cfg,
+                      double* d_out, mlmc_batch_t** out_plan);
+
+/* Replay the plan's graph on hip_stream (asynchronous). */
+int mlmc_batch_run(mlmc_batch_t* plan, void* hip_stream);
+
+/* Launch the same kernels directly, without the graph (asynchronous). */
+int mlmc_batch_run_eager(mlmc_batch_t* plan, void* hip_stream);
+
+/* Time candidate launch shapes (each replayed `repeats` times, 1..100), keep the fastest in
+ * the plan (re-captured) and in the autotune cache file named by MLMC_AUTOTUNE_CACHE (no
+ * cache when unset).  best: host, may be NULL.  Synchronous; d_out is overwritten. */
+int mlmc_batch_autotune(mlmc_batch_t* plan, int repeats, mlmc_batch_cfg_t* best);
+
+/* The plan's current launch shape and task count (host outputs, either may be NULL). */
+int mlmc_batch_info(const mlmc_batch_t* plan, mlmc_batch_cfg_t* cfg, uint64_t* n_tasks);
+
+/* Release a plan (NULL is allowed). */
+int mlmc_batch_destroy(mlmc_batch_t* plan);
+
+/* ---- learned inverse CDF (MLMC_RV_MLP) -------------------------------------------------
+ * Not in the paper: a 1-16-16-1 tanh network used as an approximate Gaussian variable in
+ * the sense of Section 2.1 / Assumption 2.1 (mirrored, so exactly zero mean; bounded).
+ * u' = min(u, 1-u), r = sqrt(-2 ln 2u'), input x = r/3.4 - 1, output y, Z~ = +-(y - r).
+ * Parameters: 321 binary32 values W1(16) b1(16) W2(16x16 row-major [out][in]) b2(16)
+ * W3(16) b3(1).  Training pairs (Philox stream 2): pair i uses words w0, w1 of counter
+ * (0, i, 2<<16, 0); even pairs take w0 mirrored to (0, 1/2), odd pairs the tail-weighted
+ * word (w0 >> 1) >> (w1 mod 31); target Phi^-1(u') + r from the binary64 exact inverse. */
+typedef struct {
+    uint64_t seed;     /* Philox key of the training pairs                               */
+    uint32_t n_pairs;  /* training set size (multiple of batch), <= 2^26                 */
+    uint32_t batch;    /* mini-batch size, a multiple of 128                              */
+    uint32_t epochs;   /* passes over the training set, 1..100000                         */
+    float lr;          /* Adam learning rate of the first epoch                           */
+    float lr_final;    /* learning rate of the last epoch (geometric decay per epoch)     */
+    uint32_t reserved;
+} mlmc_mlp_cfg_t;
+
+/* Training pairs first..first+n-1 (parity checks): d_words (device, n uint32, may be NULL)
+ * the mirrored words, d_x (device, n floats) the network inputs, d_target (device, n
+ * floats) Phi^-1(u') + r. */
+int mlmc_mlp_pairs(uint64_t seed, uint32_t first, uint32_t n, uint32_t* d_words, float* d_x,
+                   float* d_target, void* hip_stream);
+
+/* Gradient of the mean squared error over pairs first..first+n-1 (1 <= n <= 2^24) at the
+ * parameters d_params (device, 321 floats): d_grad (device, 321 floats), d_loss (device,
+ * 1 float, may be NULL).  Synchronous on hip_stream. */
+int mlmc_mlp_grad(const float* d_params, uint64_t seed, uint32_t first, uint32_t n, float* d_grad,
+                  float* d_loss, void* hip_stream);
+
+/* Train with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on cfg->n_pairs pairs; d_params
+ * (device, 321 floats) holds the initial parameters on entry and the trained ones on
+ * return.  h_loss (host, cfg->epochs floats, may be NULL) receives the mini-batch loss
+ * at the end of each epoch.  Synchronous: waits for hip_stream, then runs one captured
+ * hipGraph per epoch on a library stream. */
+int mlmc_mlp_train(const mlmc_mlp_cfg_t* cfg, float* d_params, float* h_loss, void* hip_stream);
+
+/* Deploy parameters (device, 321 floats) as the MLMC_RV_MLP inference model of the
+ * current device: each is rounded once to binary16.  Synchronous on hip_stream. */
+int mlmc_mlp_load(const float* d_params, void* hip_stream);
+
 /* Thread-local message of the last failure on this thread ("" if none). */
 const char* mlmc_last_error(void);
 

@@ -5,17 +5,19 @@ mean, bounded, finite moments, bounded density with finitely many discontinuitie
 module restates, in float64, the small network used as such an approximation:
 
     u' = min(u, 1 - u)                        (mirror: exact zero mean, like Figure 1)
-    r  = sqrt(-2 ln(2 u'))                    (input feature, r in [0, 6.7] for 32-bit words)
-    x  = r / R_SCALE - 1
+    r  = sqrt(-2 ln(2 u'))                    (r in [0, 6.7] for 32-bit words)
+    x  = r / R_SCALE - 1                      (network input)
     h1 = tanh(W1 x + b1)                      (16)
     h2 = tanh(W2 h1 + b2)                     (16 x 16)
-    y  = W3 . h2 + b3                         (approximates Phi^{-1}(u') <= 0)
-    Z~ = y for u < 1/2, -y for u >= 1/2
+    y  = W3 . h2 + b3                         (learns Phi^{-1}(u') + r, a smooth function
+                                               of r with values in [0, 0.52])
+    Z~ = y - r for u < 1/2, r - y for u >= 1/2
 
-The output is bounded (|y| <= |b3| + sum |W3|), so Assumption 2.1's boundedness holds.
-Parameters are one flat vector of 321 values in the order W1(16), b1(16), W2(16x16,
-row-major [out][in]), b2(16), W3(16), b3(1).  Training minimises the mean squared error
-to Phi^{-1}(u') with Adam (Kingma and Ba, 2015).
+Z~ is bounded for the law of 32-bit words (r <= 6.7, |y| <= |b3| + sum |W3|), so
+Assumption 2.1's boundedness holds.  Parameters are one flat vector of 321 values in the
+order W1(16), b1(16), W2(16x16, row-major [out][in]), b2(16), W3(16), b3(1).  Training
+minimises the mean squared error of y against Phi^{-1}(u') + r with Adam (Kingma and
+Ba, 2015) on pairs drawn by ``training_words``.
 
 Pinned by ``tests/test_oracle_mlp.py``: back-propagated gradients against central finite
 differences, and the Adam update against its published closed form on a scalar problem.
@@ -105,6 +107,30 @@ def adam_step(p, g, m, v, step, lr):
     return p - lr * mhat / (np.sqrt(vhat) + ADAM_EPS), m, v
 
 
+def training_words(seed, first, n):
+    """Mirrored words xm (u' = (xm + 1/2) 2^-32 < 1/2) of training pairs first..first+n-1.
+
+    Pair i takes Philox words w0, w1 of counter (0, i, 2 << 16, 0) (stream 2): even pairs
+    are uniform samples (w0 mirrored), odd pairs are tail-weighted: xm = (w0 >> 1) >> (w1 mod
+    31), which spreads the samples over the 31 dyadic scales of (0, 1/2)."""
+    from . import philox
+    i = np.arange(first, first + n, dtype=np.uint64)
+    w = philox.words(seed, 2, 0, 0, i, 2)
+    w0, w1 = w[:, 0].astype(np.uint64), w[:, 1].astype(np.uint64)
+    xm_u = np.where(w0 >= np.uint64(2 ** 31), np.uint64(2 ** 32 - 1) - w0, w0)
+    xm_t = (w0 >> np.uint64(1)) >> (w1 % np.uint64(31))
+    return np.where(i % np.uint64(2) == 0, xm_u, xm_t)
+
+
+def training_pairs(seed, first, n):
+    """(x, target) of training pairs: x the network input, target Phi^{-1}(u') + r."""
+    from scipy.special import ndtri
+    xm = training_words(seed, first, n)
+    uh = (xm.astype(np.float64) + 0.5) * 2.0 ** -32
+    r = np.sqrt(-2.0 * np.log(2.0 * uh))
+    return r / R_SCALE - 1.0, ndtri(uh) + r
+
+
 def mirror(x_words):
     """(upper-half flag, u' = min(u, 1-u)) for uint32 words, u = (x + 1/2) 2^-32."""
     x = np.asarray(x_words, dtype=np.uint64)
@@ -121,7 +147,10 @@ def deployed(p):
 def approx_icdf(x_words, p16, precision):
     """Z~ for uint32 words from the binary16-rounded parameters, evaluated in float64 and
     rounded once to precision p."""
-    s, uh = mirror(x_words)
-    y, _ = forward(p16, feature(uh))
-    z = np.where(s, -y, y)
+    shape = np.shape(x_words)
+    s, uh = mirror(np.ravel(x_words))
+    r = np.sqrt(-2.0 * np.log(2.0 * uh))
+    y, _ = forward(p16, r / R_SCALE - 1.0)
+    q = y - r
+    z = np.where(s, -q, q).reshape(shape)
     return fp.rn(precision, z)

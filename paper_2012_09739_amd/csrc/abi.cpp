@@ -16,6 +16,7 @@
 namespace mlmc {
 
 bool build_l2_table(int degree, double out[16][4]);
+hipError_t launch_mlp_deploy(const float* d_params, float* image, hipStream_t s);
 hipError_t launch_level_f64(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
 hipError_t launch_level_f32(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
 hipError_t launch_level_f16(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
@@ -80,7 +81,7 @@ struct DevState {
     double* scratch = nullptr;
     size_t scratch_bytes = 0;
     double* out8 = nullptr;             // result slot of the synchronous entry point
-    __half* mlp = nullptr;              // MlpImage
+    float* mlp = nullptr;               // MLP inference image (binary16 values as binary32)
     bool mlp_loaded = false;
 };
 
@@ -147,7 +148,7 @@ int device_state(DevState** out) {
         if ((e = hipEventCreate(&st.ev0)) != hipSuccess || (e = hipEventCreate(&st.ev1)) != hipSuccess)
             return hip_fail(e, "hipEventCreate");
         if ((e = hipMalloc(&st.out8, kPartial * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
-        if ((e = hipMalloc(&st.mlp, sizeof(MlpImage))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&st.mlp, kMlpImage * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
         rc = upload_tables(st);
         if (rc) return rc;
         st.ready = true;
@@ -236,26 +237,7 @@ uint64_t n_chunks_of(const mlmc_level_args_t* a) {
 
 LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevState& st, double* partials) {
     LevelParams p;
-    std::memset(&p, 0, sizeof p);
-    const mlmc_gbm_t& s = a->sde;
-    // binary64 constants, then one rounding to each working precision
-    const double dt = s.T * std::ldexp(1.0, -a->level);
-    const double ca = s.mu * dt;
-    const double cac = s.mu * (2.0 * dt);
-    const double cb = s.sigma * std::sqrt(dt);
-    p.ca_f64 = ca; p.cac_f64 = cac; p.cb_f64 = cb; p.x0_f64 = s.x0; p.k_f64 = s.strike;
-    p.ca_f32 = (float)ca; p.cac_f32 = (float)cac; p.cb_f32 = (float)cb; p.x0_f32 = (float)s.x0; p.k_f32 = (float)s.strike;
-    p.ca_f16 = half_of(ca); p.cac_f16 = half_of(cac); p.cb_f16 = half_of(cb);
-    p.x0_f16 = half_of(s.x0); p.k_f16 = half_of(s.strike);
-    p.payoff = s.payoff;
-    p.level = a->level;
-    p.n_steps = 1u << a->level;
-    p.n_paths = a->n_paths;
-    p.path_offset = a->path_offset;
-    p.key0 = (uint32_t)a->seed;
-    p.key1 = (uint32_t)(a->seed >> 32);
-    p.ctr2 = (a->stream << 16) | (uint32_t)a->level;
-    p.pset = a->pset;
+    fill_level_params(&p, a->sde, a->level, a->precision, a->n_paths, a->path_offset, a->seed, a->stream, a->pset);
     if (v.rv == MLMC_RV_PWL16 || v.rv == MLMC_RV_CUBIC16) {
         const int r = v.rv == MLMC_RV_PWL16 ? 0 : 1;
         p.table = st.tables[r][v.precision];
@@ -311,6 +293,58 @@ void term_mask(const Variant& v, bool m[4]) {
 }
 
 }  // namespace
+
+int set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int validate_sde_public(const mlmc_gbm_t* s) { return validate_sde(s); }
+
+// binary64 constants of one level, then one rounding to each working precision
+void fill_level_params(LevelParams* p, const mlmc_gbm_t& s, int level, int precision, uint64_t n_paths,
+                       uint64_t path_offset, uint64_t seed, uint32_t stream, uint32_t pset) {
+    (void)precision;
+    std::memset(p, 0, sizeof *p);
+    const double dt = s.T * std::ldexp(1.0, -level);
+    const double ca = s.mu * dt;
+    const double cac = s.mu * (2.0 * dt);
+    const double cb = s.sigma * std::sqrt(dt);
+    p->ca_f64 = ca; p->cac_f64 = cac; p->cb_f64 = cb; p->x0_f64 = s.x0; p->k_f64 = s.strike;
+    p->ca_f32 = (float)ca; p->cac_f32 = (float)cac; p->cb_f32 = (float)cb; p->x0_f32 = (float)s.x0;
+    p->k_f32 = (float)s.strike;
+    p->ca_f16 = half_of(ca); p->cac_f16 = half_of(cac); p->cb_f16 = half_of(cb);
+    p->x0_f16 = half_of(s.x0); p->k_f16 = half_of(s.strike);
+    p->payoff = s.payoff;
+    p->level = level;
+    p->n_steps = 1u << level;
+    p->n_paths = n_paths;
+    p->path_offset = path_offset;
+    p->key0 = (uint32_t)seed;
+    p->key1 = (uint32_t)(seed >> 32);
+    p->ctr2 = (stream << 16) | (uint32_t)level;
+    p->pset = pset;
+}
+
+int device_info(DeviceInfo* out) {
+    DevState* st;
+    int rc = device_state(&st);
+    if (rc) return rc;
+    out->n_cu = st->n_cu;
+    for (int r = 0; r < 2; ++r) {
+        for (int q = 0; q < 3; ++q) out->tables[r][q] = st->tables[r][q];
+        out->tables64[r] = st->tables64[r];
+    }
+    out->mlp = st->mlp;
+    out->mlp_loaded = st->mlp_loaded;
+    return MLMC_OK;
+}
+
 }  // namespace mlmc
 
 using namespace mlmc;
@@ -473,6 +507,18 @@ int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double
     if (rv == MLMC_RV_PWL16 || rv == MLMC_RV_CUBIC16) table = st->tables[rv == MLMC_RV_PWL16 ? 0 : 1][precision];
     hipError_t e = launch_icdf(d_words, n, rv, precision, table, st->mlp, d_out, (hipStream_t)hip_stream);
     return e == hipSuccess ? MLMC_OK : hip_fail(e, "icdf kernel launch");
+}
+
+int mlmc_mlp_load(const float* d_params, void* hip_stream) {
+    if (!d_params) return fail(MLMC_EINVAL, "d_params is NULL");
+    DevState* st;
+    int rc = device_state(&st);
+    if (rc) return rc;
+    hipError_t e = launch_mlp_deploy(d_params, st->mlp, (hipStream_t)hip_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "MLP deploy");
+    st->mlp_loaded = true;
+    return MLMC_OK;
 }
 
 int mlmc_table(int rv, int precision, double* h_out) {

@@ -62,6 +62,20 @@ hipError_t launch_uniforms(uint64_t seed, uint32_t ctr2, uint32_t pset, uint64_t
 hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, const void* table,
                        const void* mlp, double* d_out, hipStream_t s);
 
+// Device resources the library keeps for the current device (lazily initialised).
+struct DeviceInfo {
+    int n_cu;
+    const void* tables[2][3];  // [pwl, cubic][precision]
+    const double* tables64[2];
+    const void* mlp;
+    bool mlp_loaded;
+};
+int device_info(DeviceInfo* out);
+int set_error(int code, const char* fmt, ...);
+int validate_sde_public(const mlmc_gbm_t* s);
+void fill_level_params(LevelParams* p, const mlmc_gbm_t& s, int level, int precision, uint64_t n_paths,
+                       uint64_t path_offset, uint64_t seed, uint32_t stream, uint32_t pset);
+
 // Paths covered by one wave-chunk (the unit of the fixed-order reduction).
 inline uint32_t chunk_paths(int precision) { return precision == MLMC_FP16 ? 2 * kWave : kWave; }
 

@@ -5,37 +5,20 @@
 #include "internal.h"
 #include "mlp.h"
 #include "philox.h"
+#include "reduce.h"
 
 namespace mlmc {
 
 namespace {
 
-constexpr int kReduceBlock = 256;
-
-// Sums the [n_chunks][8] chunk partials in a fixed order: thread t accumulates chunks
-// t, t + 256, ... sequentially, then a fixed tree over the 256 threads.  The order
-// depends only on n_chunks, so results do not depend on the level kernel's launch shape.
+// Sums n_chunks rows of 8 chunk partials in a fixed order: thread t accumulates rows
+// t, t + 256, ... sequentially, then a fixed tree over the 256 threads.  The order depends
+// only on n_chunks, so results do not depend on the level kernel's launch shape, and the
+// batched sweep (one block per item) reproduces the single-level sums bit for bit.
 __global__ __launch_bounds__(kReduceBlock) void reduce_chunks(const double* __restrict__ partials,
                                                               uint64_t n_chunks, double* __restrict__ out) {
     __shared__ double s[kPartial][kReduceBlock];
-    double acc[kPartial];
-#pragma unroll
-    for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
-    for (uint64_t c = threadIdx.x; c < n_chunks; c += kReduceBlock) {
-#pragma unroll
-        for (int k = 0; k < kPartial; ++k) acc[k] += partials[c * kPartial + k];
-    }
-#pragma unroll
-    for (int k = 0; k < kPartial; ++k) s[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = kReduceBlock / 2; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-#pragma unroll
-            for (int k = 0; k < kPartial; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < kPartial) out[threadIdx.x] = s[threadIdx.x][0];
+    reduce_rows_block(partials, n_chunks, out, s);
 }
 
 __global__ void uniforms_kernel(uint32_t k0, uint32_t k1, uint32_t ctr2, uint32_t pset, uint64_t path0,
@@ -66,7 +49,7 @@ __global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, cons
         if constexpr (RV == MLMC_RV_EXACT) {
             z = icdf_exact_f64(w);
         } else if constexpr (RV == MLMC_RV_MLP) {
-            const float y = icdf_mlp_f32(w, (const __half*)mlp);
+            const float y = icdf_mlp_f32(w, (const float*)mlp);
             if constexpr (PREC == MLMC_FP16) z = (double)__half2float(__float2half_rn(y));
             else z = (double)y;
         } else if constexpr (PREC == MLMC_FP64) {

@@ -85,7 +85,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---- the kernel ------------------------------------------------------------------------
 // Approximate variable of one word in the working precision (binary64 or binary32).
 template <int RV, int DEG, typename T>
-__device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const __half* mlpw) {
+__device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* mlpw) {
     if constexpr (RV == MLMC_RV_MLP) {
         return (T)icdf_mlp_f32(w, mlpw);
     } else if constexpr (sizeof(T) == 8) {
@@ -95,21 +95,198 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const __half* m
     }
 }
 
+// One wave simulates one chunk of 64 paths (128 for binary16: two paths per lane) of one
+// level and writes the chunk's 8 partial sums to prm.partials[chunk].  s_tab is the
+// coefficient table in the working precision and s_tab64 the binary64 one (diagnostic),
+// both in LDS.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG>
-__global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
+__device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
+                                          const double* s_tab64) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kExactOnly = (RV == MLMC_RV_EXACT);
     constexpr bool kNeedExact = kExactOnly || NESTED;
     constexpr bool kNeedApprox = !kExactOnly;
     constexpr bool kKahan = KAHAN && PREC != MLMC_FP64;
-    constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
     constexpr int L = (PREC == MLMC_FP16) ? 2 : 1;  // paths per lane
+    using AT = typename std::conditional<PREC == MLMC_FP64, double, float>::type;
+    const AT* s_tab = (const AT*)s_tab_v;
+    const __half* s_tab16 = (const __half*)s_tab_v;
+    const float* mlpw = (const float*)s_tab_v;  // the MLP image when RV is MLMC_RV_MLP
+    constexpr uint32_t kChunk = kWave * L;
+    const uint32_t n_calls = (prm.n_steps + 3) / 4;
+
+    uint64_t local[L];
+    bool valid[L];
+    uint32_t path[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        local[l] = chunk * kChunk + (uint64_t)l * kWave + lane;
+        valid[l] = local[l] < prm.n_paths;
+        path[l] = (uint32_t)(prm.path_offset + (valid[l] ? local[l] : 0));
+    }
+
+    // exact pair (binary64)
+    double Xfh[L], Xch[L], zh_prev[L];
+    // binary64 fine path with approximate variables (diagnostic)
+    double Xft[L];
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        Xfh[l] = prm.x0_f64; Xch[l] = prm.x0_f64; zh_prev[l] = 0.0; Xft[l] = prm.x0_f64;
+    }
+    // approximate pair
+    AT Xfb = (AT)(PREC == MLMC_FP64 ? prm.x0_f64 : prm.x0_f32), Xcb = Xfb, cfb = 0, ccb = 0, zb_prev = 0;
+    const AT ca_b = (AT)(PREC == MLMC_FP64 ? prm.ca_f64 : prm.ca_f32);
+    const AT cac_b = (AT)(PREC == MLMC_FP64 ? prm.cac_f64 : prm.cac_f32);
+    const AT cb_b = (AT)(PREC == MLMC_FP64 ? prm.cb_f64 : prm.cb_f32);
+    __half2 Xf2 = __half2half2(prm.x0_f16), Xc2 = Xf2, cf2 = __float2half2_rn(0.0f), cc2 = cf2,
+            z2_prev = cf2;
+    const __half2 ca2 = __half2half2(prm.ca_f16), cac2 = __half2half2(prm.cac_f16),
+                  cb2 = __half2half2(prm.cb_f16);
+
+    for (uint32_t q = 0; q < n_calls; ++q) {
+        Words4 r[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) r[l] = philox4x32_10(q, path[l], prm.ctr2, prm.pset, prm.key0, prm.key1);
+        double zx[L][4];
+        if constexpr (kNeedExact) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (4 * q + i >= prm.n_steps) break;  // only at levels 0 and 1
+            const bool coarse = (i & 1) != 0;
+            if constexpr (kNeedExact) {
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    const double z = zx[l][i];
+                    em_step<double>(Xfh[l], z, prm.ca_f64, prm.cb_f64);
+                    if (coarse) em_step<double>(Xch[l], zh_prev[l] + z, prm.cac_f64, prm.cb_f64);
+                    else zh_prev[l] = z;
+                }
+            }
+            if constexpr (kNeedApprox && PREC != MLMC_FP16) {
+                const AT z = approx_rv<RV, DEG, AT>(r[0].w[i], s_tab, mlpw);
+                if constexpr (kKahan) {
+                    em_step_kahan<AT>(Xfb, cfb, z, ca_b, cb_b);
+                    if (coarse) em_step_kahan<AT>(Xcb, ccb, zb_prev + z, cac_b, cb_b);
+                } else {
+                    em_step<AT>(Xfb, z, ca_b, cb_b);
+                    if (coarse) em_step<AT>(Xcb, zb_prev + z, cac_b, cb_b);
+                }
+                if (!coarse) zb_prev = z;
+            }
+            if constexpr (kNeedApprox && PREC == MLMC_FP16) {
+                __half z0, z1;
+                if constexpr (RV == MLMC_RV_MLP) {
+                    z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw));
+                    z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw));
+                } else {
+                    z0 = icdf_dyadic_f16<DEG>(r[0].w[i], s_tab16);
+                    z1 = icdf_dyadic_f16<DEG>(r[1].w[i], s_tab16);
+                }
+                const __half2 z = __halves2half2(z0, z1);
+                if constexpr (kKahan) {
+                    em_step_kahan_h2(Xf2, cf2, z, ca2, cb2);
+                    if (coarse) em_step_kahan_h2(Xc2, cc2, __hadd2(z2_prev, z), cac2, cb2);
+                } else {
+                    em_step_h2(Xf2, z, ca2, cb2);
+                    if (coarse) em_step_h2(Xc2, __hadd2(z2_prev, z), cac2, cb2);
+                }
+                if (!coarse) z2_prev = z;
+            }
+            if constexpr (DIAG) {
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    double zt;
+                    if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw);
+                    else zt = icdf_dyadic_f64<DEG>(r[l].w[i], s_tab64);
+                    em_step<double>(Xft[l], zt, prm.ca_f64, prm.cb_f64);
+                }
+            }
+        }
+    }
+
+    // payoffs and differences (binary64), then the lane's contribution to the sums
+    double acc[kPartial];
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
+    const bool has_coarse = prm.level >= 1;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        double t[kTerms] = {0.0, 0.0, 0.0, 0.0};
+        double pfh = 0.0, pch = 0.0, pfb = 0.0, pcb = 0.0, xfb = 0.0;
+        if constexpr (kNeedExact) {
+            pfh = payoff<double>(Xfh[l], prm.k_f64, prm.payoff);
+            pch = has_coarse ? payoff<double>(Xch[l], prm.k_f64, prm.payoff) : 0.0;
+        }
+        if constexpr (kNeedApprox) {
+            if constexpr (PREC == MLMC_FP16) {
+                const __half xf = l == 0 ? __low2half(Xf2) : __high2half(Xf2);
+                const __half xc = l == 0 ? __low2half(Xc2) : __high2half(Xc2);
+                pfb = (double)__half2float(payoff_h(xf, prm.k_f16, prm.payoff));
+                pcb = has_coarse ? (double)__half2float(payoff_h(xc, prm.k_f16, prm.payoff)) : 0.0;
+                xfb = (double)__half2float(xf);
+            } else {
+                const AT kk = (AT)(PREC == MLMC_FP64 ? prm.k_f64 : prm.k_f32);
+                pfb = (double)payoff<AT>(Xfb, kk, prm.payoff);
+                pcb = has_coarse ? (double)payoff<AT>(Xcb, kk, prm.payoff) : 0.0;
+                xfb = (double)Xfb;
+            }
+        }
+        if constexpr (kExactOnly) {
+            t[MLMC_TERM_TWO_WAY] = pfh - pch;
+        } else {
+            t[MLMC_TERM_TWO_WAY] = pfb - pcb;
+            if constexpr (NESTED) {
+                t[MLMC_TERM_TWO_WAY_EXACT] = pfh - pch;
+                t[MLMC_TERM_FOUR_WAY] = t[MLMC_TERM_TWO_WAY_EXACT] - t[MLMC_TERM_TWO_WAY];
+            }
+            if constexpr (DIAG) t[MLMC_TERM_ROUNDING] = xfb - Xft[l];
+        }
+        if (valid[l]) {
+#pragma unroll
+            for (int k = 0; k < kTerms; ++k) {
+                acc[k] += t[k];
+                acc[kTerms + k] += t[k] * t[k];
+            }
+            const uint64_t o = local[l];
+            if constexpr (kNeedExact) {
+                if (prm.out_pf_hat) prm.out_pf_hat[o] = pfh;
+                if (prm.out_pc_hat) prm.out_pc_hat[o] = pch;
+            }
+            if constexpr (kNeedApprox) {
+                if (prm.out_pf_bar) prm.out_pf_bar[o] = pfb;
+                if (prm.out_pc_bar) prm.out_pc_bar[o] = pcb;
+            }
+            if constexpr (DIAG) {
+                if (prm.out_xf_tilde) prm.out_xf_tilde[o] = Xft[l];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane < kPartial) {
+        double v = acc[0];
+#pragma unroll
+        for (int k = 1; k < kPartial; ++k)
+            if (lane == (uint32_t)k) v = acc[k];
+        prm.partials[chunk * kPartial + lane] = v;
+    }
+}
+
+template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG>
+__global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
+    constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
+    constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
+    constexpr int L = (PREC == MLMC_FP16) ? 2 : 1;
     using AT = typename std::conditional<PREC == MLMC_FP64, double, float>::type;
 
     // coefficient tables in LDS (working precision, and binary64 for the diagnostic)
     __shared__ AT s_tab[kTableRows * 4];
     __shared__ __half s_tab16[kTableRows * 4];
     __shared__ double s_tab64[kTableRows * 4];
+    __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
     if constexpr (kDyadic) {
         for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
             if constexpr (PREC == MLMC_FP16) s_tab16[i] = ((const __half*)prm.table)[i];
@@ -118,175 +295,19 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
         }
         __syncthreads();
     }
-    const __half* mlpw = (const __half*)prm.mlp;
-
+    if constexpr (RV == MLMC_RV_MLP) {
+        for (int i = threadIdx.x; i < kMlpImage; i += blockDim.x) s_mlp[i] = ((const float*)prm.mlp)[i];
+        __syncthreads();
+    }
+    const void* tab = RV == MLMC_RV_MLP ? (const void*)s_mlp
+                                        : (PREC == MLMC_FP16 ? (const void*)s_tab16 : (const void*)s_tab);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     constexpr uint32_t kChunk = kWave * L;
     const uint64_t n_chunks = (prm.n_paths + kChunk - 1) / kChunk;
-    const uint32_t n_calls = (prm.n_steps + 3) / 4;
-
-    for (uint64_t chunk = wave; chunk < n_chunks; chunk += n_waves) {
-        uint64_t local[L];
-        bool valid[L];
-        uint32_t path[L];
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            local[l] = chunk * kChunk + (uint64_t)l * kWave + lane;
-            valid[l] = local[l] < prm.n_paths;
-            path[l] = (uint32_t)(prm.path_offset + (valid[l] ? local[l] : 0));
-        }
-
-        // exact pair (binary64)
-        double Xfh[L], Xch[L], zh_prev[L];
-        // binary64 fine path with approximate variables (diagnostic)
-        double Xft[L];
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            Xfh[l] = prm.x0_f64; Xch[l] = prm.x0_f64; zh_prev[l] = 0.0; Xft[l] = prm.x0_f64;
-        }
-        // approximate pair
-        AT Xfb = (AT)(PREC == MLMC_FP64 ? prm.x0_f64 : prm.x0_f32), Xcb = Xfb, cfb = 0, ccb = 0, zb_prev = 0;
-        const AT ca_b = (AT)(PREC == MLMC_FP64 ? prm.ca_f64 : prm.ca_f32);
-        const AT cac_b = (AT)(PREC == MLMC_FP64 ? prm.cac_f64 : prm.cac_f32);
-        const AT cb_b = (AT)(PREC == MLMC_FP64 ? prm.cb_f64 : prm.cb_f32);
-        __half2 Xf2 = __half2half2(prm.x0_f16), Xc2 = Xf2, cf2 = __float2half2_rn(0.0f), cc2 = cf2,
-                z2_prev = cf2;
-        const __half2 ca2 = __half2half2(prm.ca_f16), cac2 = __half2half2(prm.cac_f16),
-                      cb2 = __half2half2(prm.cb_f16);
-
-        for (uint32_t q = 0; q < n_calls; ++q) {
-            Words4 r[L];
-#pragma unroll
-            for (int l = 0; l < L; ++l) r[l] = philox4x32_10(q, path[l], prm.ctr2, prm.pset, prm.key0, prm.key1);
-            double zx[L][4];
-            if constexpr (kNeedExact) {
-#pragma unroll
-                for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l]);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (4 * q + i >= prm.n_steps) break;  // only at levels 0 and 1
-                const bool coarse = (i & 1) != 0;
-                if constexpr (kNeedExact) {
-#pragma unroll
-                    for (int l = 0; l < L; ++l) {
-                        const double z = zx[l][i];
-                        em_step<double>(Xfh[l], z, prm.ca_f64, prm.cb_f64);
-                        if (coarse) em_step<double>(Xch[l], zh_prev[l] + z, prm.cac_f64, prm.cb_f64);
-                        else zh_prev[l] = z;
-                    }
-                }
-                if constexpr (kNeedApprox && PREC != MLMC_FP16) {
-                    const AT z = approx_rv<RV, DEG, AT>(r[0].w[i], s_tab, mlpw);
-                    if constexpr (kKahan) {
-                        em_step_kahan<AT>(Xfb, cfb, z, ca_b, cb_b);
-                        if (coarse) em_step_kahan<AT>(Xcb, ccb, zb_prev + z, cac_b, cb_b);
-                    } else {
-                        em_step<AT>(Xfb, z, ca_b, cb_b);
-                        if (coarse) em_step<AT>(Xcb, zb_prev + z, cac_b, cb_b);
-                    }
-                    if (!coarse) zb_prev = z;
-                }
-                if constexpr (kNeedApprox && PREC == MLMC_FP16) {
-                    __half z0, z1;
-                    if constexpr (RV == MLMC_RV_MLP) {
-                        z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw));
-                        z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw));
-                    } else {
-                        z0 = icdf_dyadic_f16<DEG>(r[0].w[i], s_tab16);
-                        z1 = icdf_dyadic_f16<DEG>(r[1].w[i], s_tab16);
-                    }
-                    const __half2 z = __halves2half2(z0, z1);
-                    if constexpr (kKahan) {
-                        em_step_kahan_h2(Xf2, cf2, z, ca2, cb2);
-                        if (coarse) em_step_kahan_h2(Xc2, cc2, __hadd2(z2_prev, z), cac2, cb2);
-                    } else {
-                        em_step_h2(Xf2, z, ca2, cb2);
-                        if (coarse) em_step_h2(Xc2, __hadd2(z2_prev, z), cac2, cb2);
-                    }
-                    if (!coarse) z2_prev = z;
-                }
-                if constexpr (DIAG) {
-#pragma unroll
-                    for (int l = 0; l < L; ++l) {
-                        double zt;
-                        if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw);
-                        else zt = icdf_dyadic_f64<DEG>(r[l].w[i], s_tab64);
-                        em_step<double>(Xft[l], zt, prm.ca_f64, prm.cb_f64);
-                    }
-                }
-            }
-        }
-
-        // payoffs and differences (binary64), then the lane's contribution to the sums
-        double acc[kPartial];
-#pragma unroll
-        for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
-        const bool has_coarse = prm.level >= 1;
-#pragma unroll
-        for (int l = 0; l < L; ++l) {
-            double t[kTerms] = {0.0, 0.0, 0.0, 0.0};
-            double pfh = 0.0, pch = 0.0, pfb = 0.0, pcb = 0.0, xfb = 0.0;
-            if constexpr (kNeedExact) {
-                pfh = payoff<double>(Xfh[l], prm.k_f64, prm.payoff);
-                pch = has_coarse ? payoff<double>(Xch[l], prm.k_f64, prm.payoff) : 0.0;
-            }
-            if constexpr (kNeedApprox) {
-                if constexpr (PREC == MLMC_FP16) {
-                    const __half xf = l == 0 ? __low2half(Xf2) : __high2half(Xf2);
-                    const __half xc = l == 0 ? __low2half(Xc2) : __high2half(Xc2);
-                    pfb = (double)__half2float(payoff_h(xf, prm.k_f16, prm.payoff));
-                    pcb = has_coarse ? (double)__half2float(payoff_h(xc, prm.k_f16, prm.payoff)) : 0.0;
-                    xfb = (double)__half2float(xf);
-                } else {
-                    const AT kk = (AT)(PREC == MLMC_FP64 ? prm.k_f64 : prm.k_f32);
-                    pfb = (double)payoff<AT>(Xfb, kk, prm.payoff);
-                    pcb = has_coarse ? (double)payoff<AT>(Xcb, kk, prm.payoff) : 0.0;
-                    xfb = (double)Xfb;
-                }
-            }
-            if constexpr (kExactOnly) {
-                t[MLMC_TERM_TWO_WAY] = pfh - pch;
-            } else {
-                t[MLMC_TERM_TWO_WAY] = pfb - pcb;
-                if constexpr (NESTED) {
-                    t[MLMC_TERM_TWO_WAY_EXACT] = pfh - pch;
-                    t[MLMC_TERM_FOUR_WAY] = t[MLMC_TERM_TWO_WAY_EXACT] - t[MLMC_TERM_TWO_WAY];
-                }
-                if constexpr (DIAG) t[MLMC_TERM_ROUNDING] = xfb - Xft[l];
-            }
-            if (valid[l]) {
-#pragma unroll
-                for (int k = 0; k < kTerms; ++k) {
-                    acc[k] += t[k];
-                    acc[kTerms + k] += t[k] * t[k];
-                }
-                const uint64_t o = local[l];
-                if constexpr (kNeedExact) {
-                    if (prm.out_pf_hat) prm.out_pf_hat[o] = pfh;
-                    if (prm.out_pc_hat) prm.out_pc_hat[o] = pch;
-                }
-                if constexpr (kNeedApprox) {
-                    if (prm.out_pf_bar) prm.out_pf_bar[o] = pfb;
-                    if (prm.out_pc_bar) prm.out_pc_bar[o] = pcb;
-                }
-                if constexpr (DIAG) {
-                    if (prm.out_xf_tilde) prm.out_xf_tilde[o] = Xft[l];
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kPartial; ++k) acc[k] = wave_sum(acc[k]);
-        if (lane < kPartial) {
-            double v = acc[0];
-#pragma unroll
-            for (int k = 1; k < kPartial; ++k)
-                if (lane == (uint32_t)k) v = acc[k];
-            prm.partials[chunk * kPartial + lane] = v;
-        }
-    }
+    for (uint64_t chunk = wave; chunk < n_chunks; chunk += n_waves)
+        run_chunk<PREC, RV, NESTED, KAHAN, DIAG>(prm, chunk, lane, tab, s_tab64);
 }
 
 }  // namespace mlmc

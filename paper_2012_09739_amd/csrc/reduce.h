@@ -1,0 +1,36 @@
+// Fixed-order block reduction of chunk partial rows (shared by the single-level and the
+// batched paths so that both give bit-identical sums).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace mlmc {
+
+constexpr int kReduceBlock = 256;
+
+// blockDim.x must be kReduceBlock.  Row c holds (sum[0..3], sumsq[0..3]) of chunk c.
+__device__ __forceinline__ void reduce_rows_block(const double* __restrict__ rows, uint64_t n,
+                                                  double* __restrict__ out, double (*s)[kReduceBlock]) {
+    double acc[kPartial];
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
+    for (uint64_t c = threadIdx.x; c < n; c += kReduceBlock) {
+#pragma unroll
+        for (int k = 0; k < kPartial; ++k) acc[k] += rows[c * kPartial + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = kReduceBlock / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < kPartial; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kPartial) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+}  // namespace mlmc

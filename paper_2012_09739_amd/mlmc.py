@@ -49,6 +49,23 @@ class mlmc_level_args_t(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("n_paths", ctypes.c_uint64), ("path_offset", ctypes.c_uint64)]
 
 
+class mlmc_item_t(ctypes.Structure):
+    _fields_ = [("sde", mlmc_gbm_t), ("level", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("kahan", ctypes.c_int32), ("pset", ctypes.c_uint32), ("stream", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("n_paths", ctypes.c_uint64), ("seed", ctypes.c_uint64)]
+
+
+class mlmc_batch_cfg_t(ctypes.Structure):
+    _fields_ = [("waves_per_cu", ctypes.c_int32), ("task_steps", ctypes.c_int32),
+                ("priority_level", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class mlmc_mlp_cfg_t(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_pairs", ctypes.c_uint32), ("batch", ctypes.c_uint32),
+                ("epochs", ctypes.c_uint32), ("lr", ctypes.c_float), ("lr_final", ctypes.c_float),
+                ("reserved", ctypes.c_uint32)]
+
+
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "mlmc_init": (ctypes.c_int, [ctypes.c_int]),
@@ -63,6 +80,17 @@ _SIGNATURES = {
     "mlmc_icdf": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_table": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "mlmc_last_error": (ctypes.c_char_p, []),
+    "mlmc_batch_create": (ctypes.c_int, [ctypes.POINTER(mlmc_item_t), ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(mlmc_batch_cfg_t), _P, ctypes.POINTER(_P)]),
+    "mlmc_batch_run": (ctypes.c_int, [_P, _P]),
+    "mlmc_batch_run_eager": (ctypes.c_int, [_P, _P]),
+    "mlmc_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(mlmc_batch_cfg_t)]),
+    "mlmc_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(mlmc_batch_cfg_t), ctypes.POINTER(ctypes.c_uint64)]),
+    "mlmc_batch_destroy": (ctypes.c_int, [_P]),
+    "mlmc_mlp_pairs": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _P, _P, _P, _P]),
+    "mlmc_mlp_grad": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _P, _P, _P]),
+    "mlmc_mlp_train": (ctypes.c_int, [ctypes.POINTER(mlmc_mlp_cfg_t), _P, _P, _P]),
+    "mlmc_mlp_load": (ctypes.c_int, [_P, _P]),
 }
 
 _lib = None
@@ -176,6 +204,69 @@ def mlmc_table(rv, precision):
     buf = (ctypes.c_double * 64)()
     _check(lib().mlmc_table(rv, precision, buf))
     return [[buf[4 * j + i] for i in range(4)] for j in range(16)]
+
+
+def item(sde, level, n_paths, precision, kahan=0, seed=0, *, pset=0, stream=1):
+    """One (parameter set, level) item of a batched sweep (nested samples)."""
+    return mlmc_item_t(sde, level, precision, int(kahan), pset, stream, 0, n_paths, seed)
+
+
+def mlmc_batch_create(items, rv, d_out, cfg=None):
+    """Plan for a list of mlmc_item_t; d_out: device tensor of len(items) x 8 doubles.
+    Returns an opaque plan handle (int)."""
+    arr = (mlmc_item_t * len(items))(*items)
+    plan = ctypes.c_void_p()
+    _check(lib().mlmc_batch_create(arr, len(items), rv, ctypes.byref(cfg) if cfg is not None else None,
+                                   _ptr(d_out), ctypes.byref(plan)))
+    return plan.value
+
+
+def mlmc_batch_run(plan, stream=None):
+    _check(lib().mlmc_batch_run(plan, _stream(stream)))
+
+
+def mlmc_batch_run_eager(plan, stream=None):
+    _check(lib().mlmc_batch_run_eager(plan, _stream(stream)))
+
+
+def mlmc_batch_autotune(plan, repeats=3):
+    best = mlmc_batch_cfg_t()
+    _check(lib().mlmc_batch_autotune(plan, repeats, ctypes.byref(best)))
+    return best
+
+
+def mlmc_batch_info(plan):
+    cfg = mlmc_batch_cfg_t()
+    n = ctypes.c_uint64()
+    _check(lib().mlmc_batch_info(plan, ctypes.byref(cfg), ctypes.byref(n)))
+    return cfg, n.value
+
+
+def mlmc_batch_destroy(plan):
+    _check(lib().mlmc_batch_destroy(plan))
+
+
+def mlp_cfg(seed=0, n_pairs=2 ** 20, batch=4096, epochs=40, lr=1e-2, lr_final=1e-5):
+    return mlmc_mlp_cfg_t(seed, n_pairs, batch, epochs, lr, lr_final, 0)
+
+
+def mlmc_mlp_pairs(seed, first, n, d_x, d_target, d_words=None, stream=None):
+    _check(lib().mlmc_mlp_pairs(seed, first, n, _ptr(d_words), _ptr(d_x), _ptr(d_target), _stream(stream)))
+
+
+def mlmc_mlp_grad(d_params, seed, first, n, d_grad, d_loss=None, stream=None):
+    _check(lib().mlmc_mlp_grad(_ptr(d_params), seed, first, n, _ptr(d_grad), _ptr(d_loss), _stream(stream)))
+
+
+def mlmc_mlp_train(cfg, d_params, stream=None):
+    """Trains in place (device tensor of 321 floats); returns the per-epoch losses."""
+    hist = (ctypes.c_float * cfg.epochs)()
+    _check(lib().mlmc_mlp_train(ctypes.byref(cfg), _ptr(d_params), hist, _stream(stream)))
+    return list(hist)
+
+
+def mlmc_mlp_load(d_params, stream=None):
+    _check(lib().mlmc_mlp_load(_ptr(d_params), _stream(stream)))
 
 
 def mlmc_last_error():

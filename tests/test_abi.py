@@ -97,3 +97,16 @@ def test_library_table_matches_oracle_table(rv, deg):
     assert np.max(np.abs(got - want) / np.abs(want)) < 1e-12
     for p, dt in ((M.MLMC_FP32, np.float32), (M.MLMC_FP16, np.float16)):
         np.testing.assert_array_equal(np.array(M.mlmc_table(rv, p))[:, :deg + 1], want.astype(dt).astype(np.float64))
+
+
+def test_batch_validation_before_device():
+    s = M.gbm()
+    for bad in (M.item(s, -1, 10, M.MLMC_FP32), M.item(s, 3, 0, M.MLMC_FP32), M.item(s, 3, 10, M.MLMC_FP64),
+                M.item(s, 3, 10, M.MLMC_FP16, kahan=3), M.item(M.gbm(T=-1.0), 3, 10, M.MLMC_FP32)):
+        with pytest.raises(M.MlmcError) as e:
+            M.mlmc_batch_create([bad], M.MLMC_RV_PWL16, 1)
+        assert e.value.code == M.MLMC_EINVAL
+    with pytest.raises(M.MlmcError) as e:
+        M.mlmc_batch_create([M.item(s, 3, 10, M.MLMC_FP32)], M.MLMC_RV_EXACT, 1)
+    assert e.value.code == M.MLMC_EINVAL
+    assert M.lib().mlmc_batch_destroy(None) == M.MLMC_OK

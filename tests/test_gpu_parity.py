@@ -227,5 +227,5 @@ def test_invalid_arguments_rejected_on_gpu():
         M.mlmc_level(M.gbm(), 3, 10, M.MLMC_FP32, M.MLMC_EXACT, 0, 0)
     assert e.value.code == M.MLMC_EINVAL
     with pytest.raises(M.MlmcError) as e:
-        M.mlmc_level(M.gbm(), 3, 10, M.MLMC_FP32, M.MLMC_NESTED_MLP, 0, 0)
-    assert e.value.code == M.MLMC_EUNSUPPORTED
+        M.mlmc_level(M.gbm(T=-1.0), 3, 10, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, 0)
+    assert e.value.code == M.MLMC_EINVAL

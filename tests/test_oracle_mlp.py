@@ -47,10 +47,23 @@ def test_deployed_model_is_mirror_symmetric_and_bounded():
     zm = mlp.approx_icdf(np.uint64(2 ** 32 - 1) - x, p16, fp.FP64)
     np.testing.assert_array_equal(zm, -z)
     W1, b1, W2, b2, W3, b3 = mlp.unpack(p16)
-    assert np.abs(z).max() <= abs(b3) + np.abs(W3).sum()
+    # |Z~| <= r + |y| with r <= sqrt(64 ln 2) for 32-bit words
+    assert np.abs(z).max() <= np.sqrt(64 * np.log(2.0)) + abs(b3) + np.abs(W3).sum()
 
 
 def test_feature_range():
     # u' from 2^-33 (word 0) to just under 1/2
     x = mlp.feature(np.array([2.0 ** -33, 0.5 - 2.0 ** -33]))
     assert -1.0 <= x[1] < -0.99 and 0.9 < x[0] < 1.0
+
+
+def test_training_pairs_cover_the_tail_and_target_the_residual():
+    x, t = mlp.training_pairs(0, 0, 4096)
+    xm = mlp.training_words(0, 0, 4096)
+    assert np.all(xm < 2 ** 31)
+    uh = (xm.astype(np.float64) + 0.5) * 2.0 ** -32
+    assert np.mean(uh[1::2] < 2.0 ** -16) > 0.4          # tail-weighted odd pairs
+    assert abs(np.mean(uh[0::2]) - 0.25) < 0.02           # uniform even pairs on (0, 1/2)
+    assert t.min() > 0 and t.max() < 0.6                   # Phi^{-1}(u') + r in (0, 0.52]
+    # the residual target is small where the leading term dominates
+    assert np.all(np.abs((x + 1.0) * mlp.R_SCALE - np.sqrt(-2 * np.log(2 * uh))) < 1e-12)
