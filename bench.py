@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-speedup", action="store_true", help="skip the equal-variance legs")
+    p.add_argument("--no-reports", action="store_true",
+                   help="skip the report legs of the other workloads (fp64 plain, fp16, batch, mlp)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a device copy of known size (HBM counter calibration)")
     return p.parse_args()
@@ -115,6 +117,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         extra["copy_calibration_bytes"] = 2 * src.numel() * 4
+
+    if not a.no_reports:
+        extra["reports"] = reports(M, E, torch)
 
     cpu = None if a.no_cpu_baseline else cpu_baseline()
 
@@ -187,14 +192,124 @@ def equal_variance_report(M, E, call):
     return rep
 
 
+def _level_costs(M, sde, levels, n, prec, mode, kahan, seed=SEED):
+    rows = []
+    for l in levels:
+        M.mlmc_level(sde, l, n, prec, mode, kahan, seed)
+        rows.append(M.mlmc_level(sde, l, n, prec, mode, kahan, seed))
+    return rows
+
+
+def reports(M, E, torch):
+    """Report legs of the other workloads (not timed into `value`)."""
+    import numpy as np
+
+    import mlmc_workloads as W
+    rep = {}
+    var = lambda rows, t: [E.level_stats(r["sum"][t], r["sumsq"][t], r["n_paths"])[1] for r in rows]  # noqa: E731
+    mean = lambda rows, t: [E.level_stats(r["sum"][t], r["sumsq"][t], r["n_paths"])[0] for r in rows]  # noqa: E731
+    cost = lambda rows: [r["cost_seconds"] / r["n_paths"] for r in rows]  # noqa: E731
+    rate = lambda rows: sum(r["path_steps"] for r in rows) / sum(r["cost_seconds"] for r in rows)  # noqa: E731
+
+    # plain MLMC in binary64, exact inverse CDF: GBM, P = X_T, levels 0..5, 10^4 paths, seed 0
+    c1 = W.PLAIN_FP64
+    rows = _level_costs(M, M.gbm(), c1["levels"], c1["n_paths"], M.MLMC_FP64, M.MLMC_EXACT, 0)
+    rep["plain_fp64_levels0to5_1e4"] = {"mean": mean(rows, 0), "var": var(rows, 0),
+                                        "theta_hat": E.plain_estimate([(r["sum"][0], r["n_paths"]) for r in rows]),
+                                        "theta_limit_e^mu": math.exp(0.05), "path_steps_per_s": rate(rows)}
+
+    # packed binary16 with Kahan, piecewise cubic, binary64 exact branch: levels 0..6, 2^24 paths
+    c3 = W.NESTED_FP16
+    call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
+    nested16 = []
+    for l in c3["levels"]:
+        args = M.level_args(call, l, c3["n_paths"], M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1, SEED, diag=1)
+        out = torch.zeros(8, dtype=torch.float64, device="cuda")
+        M.mlmc_level_ex(args, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        M.mlmc_level_ex(args, out)
+        e1.record()
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        nested16.append({"sum": list(o[:4]), "sumsq": list(o[4:]), "n_paths": c3["n_paths"],
+                         "path_steps": c3["n_paths"] << l, "cost_seconds": e0.elapsed_time(e1) * 1e-3})
+    plain = _level_costs(M, call, c3["levels"], c3["n_paths"], M.MLMC_FP64, M.MLMC_EXACT, 0)
+    approx16 = _level_costs(M, call, c3["levels"], c3["n_paths"], M.MLMC_FP16, M.MLMC_APPROX_CUBIC16, 1)
+    rho = 2.0 ** -11
+    bound = [2 ** l * rho ** 2 * (1 + 0.05 * 2.0 ** -l) ** (2 * 2 ** l) * math.exp(0.04) * math.exp(0.14)
+             for l in c3["levels"]]
+    rep["nested_fp16_cubic16_kahan_levels0to6_2p24"] = {
+        "nested_path_steps_per_s": rate(nested16), "approx_two_way_path_steps_per_s": rate(approx16),
+        "plain_fp64_path_steps_per_s": rate(plain),
+        "rounding_variance": var(nested16, 3), "rounding_variance_bound_B_l": bound,
+        "four_way_var": var(nested16, 1), "two_way_exact_var": var(nested16, 2),
+        "speedup_T_hat_over_T_bar": E.speedup_equal_variance(var(plain, 0), cost(plain), var(approx16, 0),
+                                                             cost(approx16), var(nested16, 1), cost(nested16))}
+
+    # batched ragged sweep: 64 GBM parameter sets x levels 0..14, fp16 (l <= 6) / fp32 (l > 6)
+    psets = W.batch_parameter_sets(W.BATCH_PSETS, seed=0)
+    items = []
+    for p, d in enumerate(psets):
+        g = M.gbm(mu=d["mu"], sigma=d["sigma"])
+        for l in W.BATCH_LEVELS:
+            prec = M.MLMC_FP16 if l <= 6 else M.MLMC_FP32
+            items.append(M.item(g, l, W.batch_paths(l), prec, 1 if prec == M.MLMC_FP16 else 0, SEED, pset=p))
+    out = torch.zeros((len(items), 8), dtype=torch.float64, device="cuda")
+    plan = M.mlmc_batch_create(items, M.MLMC_RV_PWL16, out)
+    try:
+        best = M.mlmc_batch_autotune(plan, 2)
+        M.mlmc_batch_run(plan)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            M.mlmc_batch_run(plan)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        _, n_tasks = M.mlmc_batch_info(plan)
+    finally:
+        M.mlmc_batch_destroy(plan)
+    steps = sum(it.n_paths << it.level for it in items)
+    rep["batch_64psets_levels0to14"] = {"items": len(items), "tasks": n_tasks, "ms_per_sweep": ms,
+                                        "path_steps": steps, "path_steps_per_s": steps / ms * 1e3,
+                                        "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level]}
+
+    # learned inverse CDF: train on 2^20 pairs, nested four-way levels 0..10 at 2^22 paths vs PWL16
+    params = torch.tensor(W.mlp_initial_params(0), dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    hist = M.mlmc_mlp_train(M.mlp_cfg(n_pairs=W.MLP_TRAIN_PAIRS), params)
+    train_s = time.perf_counter() - t0
+    M.mlmc_mlp_load(params)
+    words = torch.arange(2 ** 20, dtype=torch.int64, device="cuda").mul(4096).add(2047).to(torch.int32)
+    zs = {}
+    for rv in (M.MLMC_RV_EXACT, M.MLMC_RV_MLP, M.MLMC_RV_PWL16):
+        z = torch.empty(2 ** 20, dtype=torch.float64, device="cuda")
+        M.mlmc_icdf(words, 2 ** 20, rv, M.MLMC_FP32, z)
+        zs[rv] = z
+    torch.cuda.synchronize()
+    mlp_rows = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_NESTED_MLP, 0)
+    pwl_rows = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0)
+    rep["mlp_nested_fp32_levels0to10_2p22"] = {
+        "train_seconds": train_s, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+        "mse_Z_minus_Ztilde": {"mlp": float(((zs[M.MLMC_RV_MLP] - zs[M.MLMC_RV_EXACT]) ** 2).mean()),
+                               "pwl16": float(((zs[M.MLMC_RV_PWL16] - zs[M.MLMC_RV_EXACT]) ** 2).mean())},
+        "four_way_var": {"mlp": var(mlp_rows, 1), "pwl16": var(pwl_rows, 1)},
+        "nested_path_steps_per_s": {"mlp": rate(mlp_rows), "pwl16": rate(pwl_rows)}}
+    np.seterr(all="ignore")
+    return rep
+
+
 def cpu_baseline():
     """The CPU oracle (float64 NumPy, one thread) on a bounded sample of the same workload:
-    Kahan variant, levels 0..10, 2^14 paths per level (1/128 of the GPU pass)."""
+    Kahan variant, levels 0..10, 2^16 paths per level (1/32 of the GPU pass)."""
     import numpy as np  # noqa: F401
 
     import mlmc_workloads as W
     from oracle import fp, mlmc
-    n = 2 ** 14
+    n = 2 ** 16
     t0 = time.perf_counter()
     steps = 0
     for l in LEVELS:
@@ -203,7 +318,7 @@ def cpu_baseline():
         steps += n * 2 ** l
     dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "coupled path-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "nested binary32 PWL16 with Kahan, levels 0..10, 2^14 paths/level (%d coupled "
+            "sample": "nested binary32 PWL16 with Kahan, levels 0..10, 2^16 paths/level (%d coupled "
                       "path-steps, %.1f s), single-threaded NumPy" % (steps, dt)}
 
 
