@@ -82,6 +82,7 @@ struct DevState {
     size_t scratch_bytes = 0;
     double* out8 = nullptr;             // result slot of the synchronous entry point
     float* mlp = nullptr;               // MLP inference image (binary16 values as binary32)
+    double* logtab = nullptr;           // 128 cells (f, -log f) of the table-driven log
     bool mlp_loaded = false;
 };
 
@@ -149,6 +150,19 @@ int device_state(DevState** out) {
             return hip_fail(e, "hipEventCreate");
         if ((e = hipMalloc(&st.out8, kPartial * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMalloc(&st.mlp, kMlpImage * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        {
+            // cell i covers m in [1 + i/128, 1 + (i+1)/128): f = R(1/c), l = R(-log f), c the centre
+            double h[2 * kLogCells];
+            for (int i = 0; i < kLogCells; ++i) {
+                const double c = 1.0 + (i + 0.5) / kLogCells;
+                const double f = 1.0 / c;
+                h[2 * i] = f;
+                h[2 * i + 1] = (double)(-std::log((long double)f));
+            }
+            if ((e = hipMalloc(&st.logtab, sizeof h)) != hipSuccess) return hip_fail(e, "hipMalloc");
+            if ((e = hipMemcpy(st.logtab, h, sizeof h, hipMemcpyHostToDevice)) != hipSuccess)
+                return hip_fail(e, "hipMemcpy");
+        }
         rc = upload_tables(st);
         if (rc) return rc;
         st.ready = true;
@@ -244,6 +258,7 @@ LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevS
         p.table64 = st.tables64[r];
     }
     p.mlp = st.mlp;
+    p.logtab = st.logtab;
     p.partials = partials;
     return p;
 }
@@ -342,6 +357,7 @@ int device_info(DeviceInfo* out) {
     }
     out->mlp = st->mlp;
     out->mlp_loaded = st->mlp_loaded;
+    out->logtab = st->logtab;
     return MLMC_OK;
 }
 
@@ -379,6 +395,7 @@ int mlmc_shutdown(void) {
         if (st.scratch) (void)hipFree(st.scratch);
         if (st.out8) (void)hipFree(st.out8);
         if (st.mlp) (void)hipFree(st.mlp);
+        if (st.logtab) (void)hipFree(st.logtab);
         if (st.ev0) (void)hipEventDestroy(st.ev0);
         if (st.ev1) (void)hipEventDestroy(st.ev1);
         if (st.stream) (void)hipStreamDestroy(st.stream);
@@ -505,7 +522,8 @@ int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double
     if (n == 0) return MLMC_OK;
     const void* table = nullptr;
     if (rv == MLMC_RV_PWL16 || rv == MLMC_RV_CUBIC16) table = st->tables[rv == MLMC_RV_PWL16 ? 0 : 1][precision];
-    hipError_t e = launch_icdf(d_words, n, rv, precision, table, st->mlp, d_out, (hipStream_t)hip_stream);
+    hipError_t e = launch_icdf(d_words, n, rv, precision, table, st->mlp, st->logtab, d_out,
+                               (hipStream_t)hip_stream);
     return e == hipSuccess ? MLMC_OK : hip_fail(e, "icdf kernel launch");
 }
 

@@ -43,6 +43,7 @@ struct mlmc_batch {
     uint64_t task_capacity = 0;
     const void* tab32 = nullptr;
     const void* tab16 = nullptr;
+    const void* logtab = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -65,14 +66,16 @@ template <int RV>
 __global__ __launch_bounds__(256) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
                                                     const uint4* __restrict__ tasks, uint32_t n_tasks,
                                                     uint32_t* __restrict__ counter, const float* __restrict__ tab32,
-                                                    const __half* __restrict__ tab16) {
+                                                    const __half* __restrict__ tab16, const LogCell* __restrict__ logtab) {
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
     __shared__ float s_tab32[kTableRows * 4];
     __shared__ __half s_tab16[kTableRows * 4];
+    __shared__ LogCell s_log[kLogCells];
     for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
         s_tab32[i] = tab32[i];
         s_tab16[i] = tab16[i];
     }
+    for (int i = threadIdx.x; i < kLogCells; i += blockDim.x) s_log[i] = logtab[i];
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
     for (;;) {
@@ -86,10 +89,10 @@ __global__ __launch_bounds__(256) void batch_kernel(const LevelParams* __restric
         if (task.w) __builtin_amdgcn_s_setprio(3);
         for (uint32_t c = task.y; c < task.y + task.z; ++c) {
             switch (var) {
-                case 0: run_chunk<MLMC_FP16, RV, true, false, false>(prm, c, lane, s_tab16, nullptr); break;
-                case 1: run_chunk<MLMC_FP16, RV, true, true, false>(prm, c, lane, s_tab16, nullptr); break;
-                case 2: run_chunk<MLMC_FP32, RV, true, false, false>(prm, c, lane, s_tab32, nullptr); break;
-                default: run_chunk<MLMC_FP32, RV, true, true, false>(prm, c, lane, s_tab32, nullptr); break;
+                case 0: run_chunk<MLMC_FP16, RV, true, false, false>(prm, c, lane, s_tab16, nullptr, s_log); break;
+                case 1: run_chunk<MLMC_FP16, RV, true, true, false>(prm, c, lane, s_tab16, nullptr, s_log); break;
+                case 2: run_chunk<MLMC_FP32, RV, true, false, false>(prm, c, lane, s_tab32, nullptr, s_log); break;
+                default: run_chunk<MLMC_FP32, RV, true, true, false>(prm, c, lane, s_tab32, nullptr, s_log); break;
             }
         }
         if (task.w) __builtin_amdgcn_s_setprio(0);
@@ -199,11 +202,11 @@ int enqueue(mlmc_batch* b, hipStream_t s) {
     if (b->rv == MLMC_RV_CUBIC16)
         hipLaunchKernelGGL(batch_kernel<MLMC_RV_CUBIC16>, dim3(blocks), dim3(256), 0, s, b->d_params, b->d_variant,
                            b->d_tasks, (uint32_t)b->n_tasks, b->d_counter, (const float*)b->tab32,
-                           (const __half*)b->tab16);
+                           (const __half*)b->tab16, (const LogCell*)b->logtab);
     else
         hipLaunchKernelGGL(batch_kernel<MLMC_RV_PWL16>, dim3(blocks), dim3(256), 0, s, b->d_params, b->d_variant,
                            b->d_tasks, (uint32_t)b->n_tasks, b->d_counter, (const float*)b->tab32,
-                           (const __half*)b->tab16);
+                           (const __half*)b->tab16, (const LogCell*)b->logtab);
     rc = hipck(hipGetLastError(), "batch kernel launch");
     if (rc) return rc;
     hipLaunchKernelGGL(batch_reduce, dim3((unsigned)b->items.size()), dim3(kReduceBlock), 0, s, b->d_partials,
@@ -310,6 +313,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
     const int r = rv == MLMC_RV_PWL16 ? 0 : 1;
     b->tab32 = di.tables[r][MLMC_FP32];
     b->tab16 = di.tables[r][MLMC_FP16];
+    b->logtab = di.logtab;
 
     std::vector<LevelParams> prm(n_items);
     std::vector<int> var(n_items);
@@ -342,6 +346,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
         fill_level_params(&prm[i], it.sde, it.level, it.precision, it.n_paths, 0, it.seed, it.stream, it.pset);
         prm[i].partials = b->d_partials + off[i] * kPartial;
         prm[i].mlp = di.mlp;
+        prm[i].logtab = di.logtab;
     }
     if (!rc) rc = hipck(hipMemcpy(b->d_params, prm.data(), sizeof(LevelParams) * n_items, hipMemcpyHostToDevice), "copy");
     if (!rc) rc = hipck(hipMemcpy(b->d_variant, var.data(), sizeof(int) * n_items, hipMemcpyHostToDevice), "copy");

@@ -5,7 +5,8 @@
 //
 // Exact (binary64): Phi^{-1}(u) = x g(w) with x = 2u - 1 and w = -log((1 - x)(1 + x)),
 // g an entire function of w evaluated by one polynomial in w on w <= 6.25 (more than
-// 99.9% of words, so a wavefront almost never diverges) and by one in sqrt(w) beyond.
+// 99.9% of words, so a wavefront almost never diverges) and by one in sqrt(w) beyond;
+// -log is table driven (128 cells, the table in LDS or global memory).
 // x, 1 - x and 1 + x are exact; the result is exactly odd under x -> 2^32 - 1 - x.
 //
 // Approximate (Section 2.1, Lemmas 2.2 and 2.3): a polynomial of degree 1 or 3 in the
@@ -21,33 +22,35 @@
 
 namespace mlmc {
 
-// -log(y) for normal 0 < y <= 1.  y = 2^e m with m in [1/sqrt2, sqrt2) (exact), then
-// log m = 2 atanh(s) = 2s + s^3 R(s^2) with s = (m - 1)/(m + 1), R a fitted polynomial;
-// the reciprocal of m + 1 is refined by two Newton steps from the hardware estimate.
-// Absolute error about 1e-16 plus one rounding of the result.
-__device__ __forceinline__ double neg_log_f64(double y) {
-    constexpr double kR[] = MLMC_LOG_COEFFS;
-    int e = __builtin_amdgcn_frexp_exp(y);
-    double m = __builtin_amdgcn_frexp_mant(y);  // [1/2, 1)
-    const bool low = m < 0.70710678118654752440;
-    m = low ? m + m : m;
-    e = low ? e - 1 : e;
-    const double f = m - 1.0;  // exact
-    const double d = m + 1.0;
-    double r = __builtin_amdgcn_rcp(d);
-    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-    const double sv = f * r;
-    const double z = sv * sv;
-    double acc = kR[MLMC_LOG_DEG];
+// Cell of the table-driven log: f = R(1/c) for the cell centre c, l = -log(f) rounded.
+struct LogCell {
+    double f;
+    double l;
+};
+constexpr int kLogCells = 128;
+
+// -log(y) for normal 0 < y <= 1 (Tang's table method).  y = 2^(e-1023) m with m in [1, 2)
+// read off the bit pattern; the top 7 mantissa bits pick a cell (centre c, f = R(1/c));
+// r = R(m f - 1) with |r| <= 2^-8, and log y = (e - 1023) ln2 - log f + log1p(r).  Storing
+// -log f (not log c) makes the rounding of f harmless.  Absolute error about 1e-16 plus
+// the rounding of the result.
+__device__ __forceinline__ double neg_log_f64(double y, const LogCell* __restrict__ tab) {
+    constexpr double kP[] = MLMC_LOG1P_COEFFS;
+    const uint32_t hi = (uint32_t)__double2hiint(y);
+    const uint32_t lo = (uint32_t)__double2loint(y);
+    const int k = (int)((hi >> 20) & 0x7FFu) - 1023;
+    const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FF00000u), (int)lo);
+    const LogCell c = tab[(hi >> 13) & (kLogCells - 1)];
+    const double r = __builtin_fma(m, c.f, -1.0);
+    double p = kP[MLMC_LOG1P_DEG];
 #pragma unroll
-    for (int i = MLMC_LOG_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, z, kR[i]);
-    const double log_m = __builtin_fma(sv * z, acc, sv + sv);
-    const double ed = (double)e;
-    // ln 2 split so that e * kLn2Hi is exact for |e| < 2^11
+    for (int i = MLMC_LOG1P_DEG - 1; i >= 0; --i) p = __builtin_fma(p, r, kP[i]);
+    const double log_m = c.l + __builtin_fma(r * r, p, r);
+    const double kd = (double)k;
+    // ln 2 split so that k * kLn2Hi is exact for |k| < 2^11
     constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;
     constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
-    return -__builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, log_m));
+    return -__builtin_fma(kd, kLn2Hi, __builtin_fma(kd, kLn2Lo, log_m));
 }
 
 // g(w) on the tail w > 6.25 (fewer than one word in a thousand): out of line so that its
@@ -61,12 +64,12 @@ __device__ __noinline__ double icdf_tail_g(double w) {
     return acc;
 }
 
-__device__ __forceinline__ double icdf_exact_f64(uint32_t word) {
+__device__ __forceinline__ double icdf_exact_f64(uint32_t word, const LogCell* __restrict__ tab) {
     // x = 2u - 1 = (v + 1/2) 2^-31 with v = word - 2^31 (exact in binary64)
     const int32_t v = (int32_t)(word ^ 0x80000000u);
     const double x = __builtin_fma((double)v, 0x1p-31, 0x1p-32);
     const double y = (1.0 - x) * (1.0 + x);
-    const double w = neg_log_f64(y);
+    const double w = neg_log_f64(y, tab);
     constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
     double g;
     if (w <= MLMC_ICDF_W1) {
@@ -92,42 +95,16 @@ __device__ __forceinline__ double sgpr_const(double c) {
 // Exact variables of four words at once: the four Horner chains share every
 // coefficient (one scalar materialisation per coefficient for four FMAs) and give the
 // scheduler four independent dependency chains.
-__device__ __forceinline__ void icdf_exact_f64x4(const uint32_t (&word)[4], double (&z)[4]) {
-    constexpr double kR[] = MLMC_LOG_COEFFS;
+__device__ __forceinline__ void icdf_exact_f64x4(const uint32_t (&word)[4], double (&z)[4],
+                                                 const LogCell* __restrict__ tab) {
     constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
-    double x[4], sv[4], zz[4], acc[4], ed[4];
+    double x[4], w[4], d[4], acc[4];
+    bool tail = false;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int32_t v = (int32_t)(word[k] ^ 0x80000000u);
         x[k] = __builtin_fma((double)v, 0x1p-31, 0x1p-32);
-        const double y = (1.0 - x[k]) * (1.0 + x[k]);
-        int e = __builtin_amdgcn_frexp_exp(y);
-        double m = __builtin_amdgcn_frexp_mant(y);
-        const bool low = m < 0.70710678118654752440;
-        m = low ? m + m : m;
-        e = low ? e - 1 : e;
-        ed[k] = (double)e;
-        const double f = m - 1.0;
-        const double d = m + 1.0;
-        double r = __builtin_amdgcn_rcp(d);
-        r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-        r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-        sv[k] = f * r;
-        zz[k] = sv[k] * sv[k];
-        acc[k] = kR[MLMC_LOG_DEG];
-    }
-#pragma unroll
-    for (int i = MLMC_LOG_DEG - 1; i >= 0; --i) {
-        const double c = sgpr_const(kR[i]);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = __builtin_fma(acc[k], zz[k], c);
-    }
-    double w[4], d[4];
-    bool tail = false;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double log_m = __builtin_fma(sv[k] * zz[k], acc[k], sv[k] + sv[k]);
-        w[k] = -__builtin_fma(ed[k], 0x1.62e42fefa3800p-1, __builtin_fma(ed[k], 0x1.ef35793c76730p-45, log_m));
+        w[k] = neg_log_f64((1.0 - x[k]) * (1.0 + x[k]), tab);
         tail |= w[k] > MLMC_ICDF_W1;
         d[k] = w[k] - MLMC_ICDF_MID1;
         acc[k] = kCentral[MLMC_ICDF_CENTRAL_DEG];

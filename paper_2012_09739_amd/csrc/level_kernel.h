@@ -85,9 +85,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---- the kernel ------------------------------------------------------------------------
 // Approximate variable of one word in the working precision (binary64 or binary32).
 template <int RV, int DEG, typename T>
-__device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* mlpw) {
+__device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* mlpw, const LogCell* logtab) {
     if constexpr (RV == MLMC_RV_MLP) {
-        return (T)icdf_mlp_f32(w, mlpw);
+        return (T)icdf_mlp_f32(w, mlpw, logtab);
     } else if constexpr (sizeof(T) == 8) {
         return icdf_dyadic_f64<DEG>(w, (const double*)tab);
     } else {
@@ -101,7 +101,7 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
 // both in LDS.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG>
 __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
-                                          const double* s_tab64) {
+                                          const double* s_tab64, const LogCell* s_log) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kExactOnly = (RV == MLMC_RV_EXACT);
     constexpr bool kNeedExact = kExactOnly || NESTED;
@@ -150,7 +150,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
         double zx[L][4];
         if constexpr (kNeedExact) {
 #pragma unroll
-            for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l]);
+            for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], s_log);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -166,7 +166,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
                 }
             }
             if constexpr (kNeedApprox && PREC != MLMC_FP16) {
-                const AT z = approx_rv<RV, DEG, AT>(r[0].w[i], s_tab, mlpw);
+                const AT z = approx_rv<RV, DEG, AT>(r[0].w[i], s_tab, mlpw, s_log);
                 if constexpr (kKahan) {
                     em_step_kahan<AT>(Xfb, cfb, z, ca_b, cb_b);
                     if (coarse) em_step_kahan<AT>(Xcb, ccb, zb_prev + z, cac_b, cb_b);
@@ -179,8 +179,8 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
             if constexpr (kNeedApprox && PREC == MLMC_FP16) {
                 __half z0, z1;
                 if constexpr (RV == MLMC_RV_MLP) {
-                    z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw));
-                    z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw));
+                    z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw, s_log));
+                    z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw, s_log));
                 } else {
                     z0 = icdf_dyadic_f16<DEG>(r[0].w[i], s_tab16);
                     z1 = icdf_dyadic_f16<DEG>(r[1].w[i], s_tab16);
@@ -199,7 +199,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     double zt;
-                    if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw);
+                    if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw, s_log);
                     else zt = icdf_dyadic_f64<DEG>(r[l].w[i], s_tab64);
                     em_step<double>(Xft[l], zt, prm.ca_f64, prm.cb_f64);
                 }
@@ -287,6 +287,12 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
     __shared__ __half s_tab16[kTableRows * 4];
     __shared__ double s_tab64[kTableRows * 4];
     __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
+    constexpr bool kNeedLog = RV == MLMC_RV_EXACT || NESTED || RV == MLMC_RV_MLP;
+    __shared__ LogCell s_log[kNeedLog ? kLogCells : 1];
+    if constexpr (kNeedLog) {
+        for (int i = threadIdx.x; i < kLogCells; i += blockDim.x) s_log[i] = ((const LogCell*)prm.logtab)[i];
+        __syncthreads();
+    }
     if constexpr (kDyadic) {
         for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
             if constexpr (PREC == MLMC_FP16) s_tab16[i] = ((const __half*)prm.table)[i];
@@ -307,7 +313,7 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
     constexpr uint32_t kChunk = kWave * L;
     const uint64_t n_chunks = (prm.n_paths + kChunk - 1) / kChunk;
     for (uint64_t chunk = wave; chunk < n_chunks; chunk += n_waves)
-        run_chunk<PREC, RV, NESTED, KAHAN, DIAG>(prm, chunk, lane, tab, s_tab64);
+        run_chunk<PREC, RV, NESTED, KAHAN, DIAG>(prm, chunk, lane, tab, s_tab64, s_log);
 }
 
 }  // namespace mlmc

@@ -31,9 +31,9 @@ __device__ __forceinline__ float tanh_fast(float a) {
 }
 
 // r = sqrt(-2 ln(2u')) for the mirrored word xm, u' = (xm + 1/2) 2^-32.
-__device__ __forceinline__ double mlp_radius(uint32_t xm) {
+__device__ __forceinline__ double mlp_radius(uint32_t xm, const LogCell* __restrict__ logtab) {
     const double two_u = ((double)xm + 0.5) * 0x1p-31;  // exact
-    return __builtin_sqrt(2.0 * neg_log_f64(two_u));
+    return __builtin_sqrt(2.0 * neg_log_f64(two_u, logtab));
 }
 
 // Network output for input x; W is the binary32 image of the binary16 parameters (LDS).
@@ -56,10 +56,11 @@ __device__ __forceinline__ float mlp_eval(float x, const float* __restrict__ W) 
     return y;
 }
 
-__device__ __forceinline__ float icdf_mlp_f32(uint32_t word, const float* __restrict__ W) {
+__device__ __forceinline__ float icdf_mlp_f32(uint32_t word, const float* __restrict__ W,
+                                              const LogCell* __restrict__ logtab) {
     const bool upper = (word >> 31) != 0;
     const uint32_t xm = upper ? ~word : word;
-    const double r = mlp_radius(xm);
+    const double r = mlp_radius(xm, logtab);
     const float x = (float)(r * (1.0 / 3.4) - 1.0);
     const float q = mlp_eval(x, W) - (float)r;
     return upper ? -q : q;
