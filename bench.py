@@ -37,7 +37,7 @@ SEED = 0
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 # algorithmic VALU lane-operations per coupled path-step of the nested binary32
 # piecewise-linear kernel with Kahan updates (operation list in the design doc)
-ALG_OPS_PER_STEP = 94.5
+ALG_OPS_PER_STEP = 82.0
 
 
 def parse():

@@ -82,7 +82,7 @@ struct DevState {
     size_t scratch_bytes = 0;
     double* out8 = nullptr;             // result slot of the synchronous entry point
     float* mlp = nullptr;               // MLP inference image (binary16 values as binary32)
-    double* logtab = nullptr;           // 128 cells (f, -log f) of the table-driven log
+    double* logtab = nullptr;           // 256 cells (f, -log f) of the table-driven log
     bool mlp_loaded = false;
 };
 
@@ -151,10 +151,11 @@ int device_state(DevState** out) {
         if ((e = hipMalloc(&st.out8, kPartial * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMalloc(&st.mlp, kMlpImage * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
         {
-            // cell i covers m in [1 + i/128, 1 + (i+1)/128): f = R(1/c), l = R(-log f), c the centre
+            // cell i covers the frexp mantissa m in [(1 + i/256)/2, (1 + (i+1)/256)/2):
+            // f = R(1/c), l = R(-log f), c the centre
             double h[2 * kLogCells];
             for (int i = 0; i < kLogCells; ++i) {
-                const double c = 1.0 + (i + 0.5) / kLogCells;
+                const double c = 0.5 + (i + 0.5) / (2.0 * kLogCells);
                 const double f = 1.0 / c;
                 h[2 * i] = f;
                 h[2 * i + 1] = (double)(-std::log((long double)f));

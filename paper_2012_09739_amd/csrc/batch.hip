@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const LevelParams* __restric
     __shared__ __half s_tab16[kTableRows * 4];
     __shared__ LogCell s_log[kLogCells];
     for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
-        s_tab32[i] = tab32[i];
+        s_tab32[i] = prescaled_coeff(tab32[i], i % (DEG + 1));
         s_tab16[i] = tab16[i];
     }
     for (int i = threadIdx.x; i < kLogCells; i += blockDim.x) s_log[i] = logtab[i];

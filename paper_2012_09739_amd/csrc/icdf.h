@@ -4,10 +4,11 @@
 // Z~ = Phi~^{-1}(U) through the same uniform U; here U = (x + 1/2) 2^-32 for a word x.
 //
 // Exact (binary64): Phi^{-1}(u) = x g(w) with x = 2u - 1 and w = -log((1 - x)(1 + x)),
-// g an entire function of w evaluated by one polynomial in w on w <= 6.25 (more than
-// 99.9% of words, so a wavefront almost never diverges) and by one in sqrt(w) beyond;
-// -log is table driven (128 cells, the table in LDS or global memory).
-// x, 1 - x and 1 + x are exact; the result is exactly odd under x -> 2^32 - 1 - x.
+// g an entire function of w evaluated by one polynomial in w on w <= 6 (99.88% of words;
+// fewer than one wavefront in ten sees a tail word in a given slot) and by one in sqrt(w)
+// beyond; -log is table driven (256 cells, the table in LDS or global memory).
+// x is exact and y = 1 - x^2 = (1 - x)(1 + x) is rounded once (one fma); the result is
+// exactly odd under word -> 2^32 - 1 - word.
 //
 // Approximate (Section 2.1, Lemmas 2.2 and 2.3): a polynomial of degree 1 or 3 in the
 // local coordinate t of one of 16 dyadic intervals of (0, 1/2] -- I_j = [2^-(j+1), 2^-j)
@@ -22,66 +23,36 @@
 
 namespace mlmc {
 
-// Cell of the table-driven log: f = R(1/c) for the cell centre c, l = -log(f) rounded.
+// Cell of the table-driven log: f = R(1/c) for the cell centre c in [1/2, 1), l = -log(f)
+// rounded.
 struct LogCell {
     double f;
     double l;
 };
-constexpr int kLogCells = 128;
+constexpr int kLogCells = 256;
 
-// -log(y) for normal 0 < y <= 1 (Tang's table method).  y = 2^(e-1023) m with m in [1, 2)
-// read off the bit pattern; the top 7 mantissa bits pick a cell (centre c, f = R(1/c));
-// r = R(m f - 1) with |r| <= 2^-8, and log y = (e - 1023) ln2 - log f + log1p(r).  Storing
-// -log f (not log c) makes the rounding of f harmless.  Absolute error about 1e-16 plus
-// the rounding of the result.
-__device__ __forceinline__ double neg_log_f64(double y, const LogCell* __restrict__ tab) {
+// -log(y) for normal 0 < y < 1 (Tang's table method).  y = m 2^e with m in [1/2, 1) from
+// the hardware frexp; the top 8 mantissa bits pick a cell (centre c, f = R(1/c)),
+// r = R(m f - 1) with |r| <= 2^-9, and log y = e ln2 - log f + log1p(r).  Storing -log f
+// (not log c) makes the rounding of f harmless; for y in [1/2, 1) the exponent is 0 and no
+// cancellation against e ln2 occurs.  Absolute error about 1e-16 plus the rounding of the
+// result.
+__device__ __forceinline__ double neg_log_f64(double y, const LogCell* __restrict__ tab,
+                                              double p_top = 0.0, bool p_top_given = false) {
     constexpr double kP[] = MLMC_LOG1P_COEFFS;
     const uint32_t hi = (uint32_t)__double2hiint(y);
-    const uint32_t lo = (uint32_t)__double2loint(y);
-    const int k = (int)((hi >> 20) & 0x7FFu) - 1023;
-    const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FF00000u), (int)lo);
-    const LogCell c = tab[(hi >> 13) & (kLogCells - 1)];
+    const double m = __builtin_amdgcn_frexp_mant(y);
+    const double kd = (double)__builtin_amdgcn_frexp_exp(y);
+    const LogCell c = tab[(hi >> 12) & (kLogCells - 1)];
     const double r = __builtin_fma(m, c.f, -1.0);
-    double p = kP[MLMC_LOG1P_DEG];
+    double p = p_top_given ? p_top : kP[MLMC_LOG1P_DEG];
 #pragma unroll
     for (int i = MLMC_LOG1P_DEG - 1; i >= 0; --i) p = __builtin_fma(p, r, kP[i]);
     const double log_m = c.l + __builtin_fma(r * r, p, r);
-    const double kd = (double)k;
-    // ln 2 split so that k * kLn2Hi is exact for |k| < 2^11
-    constexpr double kLn2Hi = 0x1.62e42fefa3800p-1;
-    constexpr double kLn2Lo = 0x1.ef35793c76730p-45;
-    return -__builtin_fma(kd, kLn2Hi, __builtin_fma(kd, kLn2Lo, log_m));
-}
-
-// g(w) on the tail w > 6.25 (fewer than one word in a thousand): out of line so that its
-// coefficients are materialised only when a lane needs them.
-__device__ __noinline__ double icdf_tail_g(double w) {
-    constexpr double kTail[] = MLMC_ICDF_TAIL_COEFFS;
-    double acc = kTail[MLMC_ICDF_TAIL_DEG];
-    const double d = __builtin_sqrt(w) - MLMC_ICDF_MID2;
-#pragma unroll
-    for (int i = MLMC_ICDF_TAIL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, d, kTail[i]);
-    return acc;
-}
-
-__device__ __forceinline__ double icdf_exact_f64(uint32_t word, const LogCell* __restrict__ tab) {
-    // x = 2u - 1 = (v + 1/2) 2^-31 with v = word - 2^31 (exact in binary64)
-    const int32_t v = (int32_t)(word ^ 0x80000000u);
-    const double x = __builtin_fma((double)v, 0x1p-31, 0x1p-32);
-    const double y = (1.0 - x) * (1.0 + x);
-    const double w = neg_log_f64(y, tab);
-    constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
-    double g;
-    if (w <= MLMC_ICDF_W1) {
-        double acc = kCentral[MLMC_ICDF_CENTRAL_DEG];
-        const double d = w - MLMC_ICDF_MID1;
-#pragma unroll
-        for (int i = MLMC_ICDF_CENTRAL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, d, kCentral[i]);
-        g = acc;
-    } else {
-        g = icdf_tail_g(w);
-    }
-    return x * g;
+    // e ln 2 with ln 2 rounded once: the error |e| 2.3e-17 vanishes for y in [1/2, 1), where
+    // w = -log y is small, and stays below 1e-15 absolute (relative 3e-17 of w) at y = 2^-32
+    constexpr double kLn2 = 0x1.62e42fefa39efp-1;
+    return -__builtin_fma(kd, kLn2, log_m);
 }
 
 // Places a binary64 constant in an SGPR pair at its point of use.  The polynomial
@@ -92,30 +63,85 @@ __device__ __forceinline__ double sgpr_const(double c) {
     return c;
 }
 
+// g(w) on the tail w > 6 (about one word in eight hundred): out of line so that its
+// coefficients are materialised only when a lane needs them.
+__device__ __noinline__ double icdf_tail_g(double w) {
+    constexpr double kTail[] = MLMC_ICDF_TAIL_COEFFS;
+    double acc = kTail[MLMC_ICDF_TAIL_DEG];
+    const double d = __builtin_sqrt(w) - MLMC_ICDF_MID2;
+#pragma unroll
+    for (int i = MLMC_ICDF_TAIL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, d, sgpr_const(kTail[i]));
+    return acc;
+}
+
+// x = 2u - 1 = word 2^-31 + (2^-32 - 1), exact in binary64 (a multiple of 2^-32 below 1 in
+// magnitude), and y = (1 - x)(1 + x) = 1 - x^2 rounded once.
+__device__ __forceinline__ double icdf_x(uint32_t word) {
+    return __builtin_fma((double)word, 0x1p-31, 0x1p-32 - 1.0);
+}
+__device__ __forceinline__ double icdf_y(double x) {
+    return __builtin_fma(-x, x, 1.0);
+}
+
+__device__ __forceinline__ double icdf_exact_f64(uint32_t word, const LogCell* __restrict__ tab) {
+    const double x = icdf_x(word);
+    const double w = neg_log_f64(icdf_y(x), tab);
+    constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
+    double g;
+    if (w <= MLMC_ICDF_W1) {
+        double acc = kCentral[MLMC_ICDF_CENTRAL_DEG];
+#pragma unroll
+        for (int i = MLMC_ICDF_CENTRAL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, w, kCentral[i]);
+        g = acc;
+    } else {
+        g = icdf_tail_g(w);
+    }
+    return x * g;
+}
+
+// Binary64 constants held in VGPRs for a whole chunk.  Each is an operand of an fma whose
+// other constant operand is already scalar; an instruction reads at most one scalar
+// register here, so without this each use would cost a move.
+struct ExactConsts {
+    double x0;     // 2^-32 - 1, the addend of x = word 2^-31 + x0
+    double p_top;  // leading log1p coefficient
+    double g_top;  // leading central coefficient
+};
+
+__device__ __forceinline__ ExactConsts exact_consts() {
+    constexpr double kP[] = MLMC_LOG1P_COEFFS;
+    constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
+    ExactConsts k{0x1p-32 - 1.0, kP[MLMC_LOG1P_DEG], kCentral[MLMC_ICDF_CENTRAL_DEG]};
+    asm volatile("" : "+v"(k.x0), "+v"(k.p_top), "+v"(k.g_top));
+    return k;
+}
+
 // Exact variables of four words at once: the four Horner chains share every
 // coefficient (one scalar materialisation per coefficient for four FMAs) and give the
 // scheduler four independent dependency chains.
 __device__ __forceinline__ void icdf_exact_f64x4(const uint32_t (&word)[4], double (&z)[4],
-                                                 const LogCell* __restrict__ tab) {
+                                                 const LogCell* __restrict__ tab, const ExactConsts& kc) {
     constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
-    double x[4], w[4], d[4], acc[4];
-    bool tail = false;
+    double x[4], w[4], acc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int32_t v = (int32_t)(word[k] ^ 0x80000000u);
-        x[k] = __builtin_fma((double)v, 0x1p-31, 0x1p-32);
-        w[k] = neg_log_f64((1.0 - x[k]) * (1.0 + x[k]), tab);
-        tail |= w[k] > MLMC_ICDF_W1;
-        d[k] = w[k] - MLMC_ICDF_MID1;
-        acc[k] = kCentral[MLMC_ICDF_CENTRAL_DEG];
+        x[k] = __builtin_fma((double)word[k], sgpr_const(0x1p-31), kc.x0);
+        w[k] = neg_log_f64(icdf_y(x[k]), tab, kc.p_top, true);
+    }
+    {
+        const double c = sgpr_const(kCentral[MLMC_ICDF_CENTRAL_DEG - 1]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = __builtin_fma(kc.g_top, w[k], c);
     }
 #pragma unroll
-    for (int i = MLMC_ICDF_CENTRAL_DEG - 1; i >= 0; --i) {
+    for (int i = MLMC_ICDF_CENTRAL_DEG - 2; i >= 0; --i) {
         const double c = sgpr_const(kCentral[i]);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = __builtin_fma(acc[k], d[k], c);
+        for (int k = 0; k < 4; ++k) acc[k] = __builtin_fma(acc[k], w[k], c);
     }
-    if (tail) {
+    // one comparison for the four words; the per-word tests run only when some lane of
+    // the wavefront has a tail word
+    if (__builtin_fmax(__builtin_fmax(w[0], w[1]), __builtin_fmax(w[2], w[3])) > MLMC_ICDF_W1) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (w[k] > MLMC_ICDF_W1) acc[k] = icdf_tail_g(w[k]);
@@ -129,31 +155,40 @@ __device__ __forceinline__ void icdf_exact_f64x4(const uint32_t (&word)[4], doub
 struct DyadicPos {
     uint32_t row;
     uint32_t T;
-    bool upper;
+    uint32_t sign;  // 0x80000000 on the upper half, else 0 (xor into the result's sign bit)
 };
 
+// Branch-free: with xm the mirrored word (u' = (xm + 1/2) 2^-32 in I_k, k = clz(xm)) and
+// a = 2 xm + 1, clz(a) = k - 1 and, for s = min(k - 1, 14),
+//   k <= 15:  (a << s) mod 2^31 = (xm << k) - 2^31 + 2^(k-1)    (u' = 2^-(k+1) (1 + t))
+//   k >= 16:  (a << s)          = (xm << 15) + 2^14             (u' = 2^-16 t)
 __device__ __forceinline__ DyadicPos dyadic_locate(uint32_t word) {
     DyadicPos p;
-    p.upper = (word >> 31) != 0;
-    const uint32_t xm = p.upper ? ~word : word;  // 2^32 - 1 - word on the upper half
-    const uint32_t k = (uint32_t)__clz((int)xm);  // 1..32 since xm < 2^31
-    if (k <= 15u) {
-        // u' = 2^-(k+1) (1 + t):  t = ((xm << k) - 2^31 + 2^(k-1)) 2^-31
-        p.T = ((xm << k) & 0x7FFFFFFFu) + (1u << (k - 1u));
-        p.row = k - 1u;
-    } else {
-        // u' = 2^-16 t:  t = (xm + 1/2) 2^-16 = ((xm << 15) + 2^14) 2^-31
-        p.T = (xm << 15) + (1u << 14);
-        p.row = 15u;
-    }
+    p.sign = word & 0x80000000u;
+    const uint32_t xm = word ^ (uint32_t)((int32_t)word >> 31);  // 2^32 - 1 - word on the upper half
+    const uint32_t a = (xm << 1) | 1u;
+    const uint32_t km1 = (uint32_t)__builtin_clz(a);  // a != 0
+    p.T = (a << (km1 < 14u ? km1 : 14u)) & 0x7FFFFFFFu;
+    p.row = km1 < 15u ? km1 : 15u;
     return p;
 }
 
-// Z~ in binary32; tab holds 16 rows of (DEG + 1) binary32 coefficients c_0..c_d.
-template <int DEG>
+__device__ __forceinline__ float apply_sign(float q, uint32_t sign) {
+    return __uint_as_float(__float_as_uint(q) ^ sign);
+}
+__device__ __forceinline__ double apply_sign(double q, uint32_t sign) {
+    return __hiloint2double((int)((uint32_t)__double2hiint(q) ^ sign), __double2loint(q));
+}
+
+// Z~ in binary32; tab holds 16 rows of (DEG + 1) binary32 coefficients c_0..c_d, or, with
+// kPrescaled, c_i 2^(-31 i) (see prescaled_coeff): then T itself serves as the coordinate and
+// every Horner value is the unscaled one times an exact power of two (all stay normal), so
+// the result is bit-for-bit the same with one multiplication less.
+template <int DEG, bool kPrescaled = false>
 __device__ __forceinline__ float icdf_dyadic_f32(uint32_t word, const float* __restrict__ tab) {
     const DyadicPos p = dyadic_locate(word);
-    const float t = (float)p.T * 0x1p-31f;  // one correctly rounded conversion: R_32(t)
+    // one correctly rounded conversion: R_32(t) = R_32(T) 2^-31
+    const float t = kPrescaled ? (float)p.T : (float)p.T * 0x1p-31f;
     const float* c = tab + p.row * (DEG + 1);
     float q = c[DEG];
 #pragma unroll
@@ -161,7 +196,12 @@ __device__ __forceinline__ float icdf_dyadic_f32(uint32_t word, const float* __r
         q = __fmul_rn(q, t);
         q = __fadd_rn(q, c[i]);
     }
-    return p.upper ? -q : q;
+    return apply_sign(q, p.sign);
+}
+
+// Coefficient i of a row, scaled for icdf_dyadic_f32<DEG, true> (exact: a power of two).
+__device__ __forceinline__ float prescaled_coeff(float c, int i) {
+    return __builtin_ldexpf(c, -31 * i);
 }
 
 // Z~ in binary64 (the high-precision approximate variable of the diagnostic paths).
@@ -176,7 +216,7 @@ __device__ __forceinline__ double icdf_dyadic_f64(uint32_t word, const double* _
         q = __dmul_rn(q, t);
         q = __dadd_rn(q, c[i]);
     }
-    return p.upper ? -q : q;
+    return apply_sign(q, p.sign);
 }
 
 // Z~ in binary16 for one word; the coordinate is formed in binary32 and narrowed,
@@ -192,7 +232,7 @@ __device__ __forceinline__ __half icdf_dyadic_f16(uint32_t word, const __half* _
         q = __hmul(q, t);
         q = __hadd(q, c[i]);
     }
-    return p.upper ? __hneg(q) : q;
+    return p.sign ? __hneg(q) : q;
 }
 
 }  // namespace mlmc

@@ -91,14 +91,14 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
     } else if constexpr (sizeof(T) == 8) {
         return icdf_dyadic_f64<DEG>(w, (const double*)tab);
     } else {
-        return icdf_dyadic_f32<DEG>(w, (const float*)tab);
+        return icdf_dyadic_f32<DEG, true>(w, (const float*)tab);  // table staged prescaled
     }
 }
 
 // One wave simulates one chunk of 64 paths (128 for binary16: two paths per lane) of one
 // level and writes the chunk's 8 partial sums to prm.partials[chunk].  s_tab is the
-// coefficient table in the working precision and s_tab64 the binary64 one (diagnostic),
-// both in LDS.
+// coefficient table in the working precision (binary32: prescaled, see prescaled_coeff) and
+// s_tab64 the binary64 one (diagnostic), both in LDS.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG>
 __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
                                           const double* s_tab64, const LogCell* s_log) {
@@ -143,6 +143,8 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
     const __half2 ca2 = __half2half2(prm.ca_f16), cac2 = __half2half2(prm.cac_f16),
                   cb2 = __half2half2(prm.cb_f16);
 
+    ExactConsts kc{};
+    if constexpr (kNeedExact) kc = exact_consts();
     for (uint32_t q = 0; q < n_calls; ++q) {
         Words4 r[L];
 #pragma unroll
@@ -150,7 +152,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
         double zx[L][4];
         if constexpr (kNeedExact) {
 #pragma unroll
-            for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], s_log);
+            for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], s_log, kc);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -296,6 +298,7 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
     if constexpr (kDyadic) {
         for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
             if constexpr (PREC == MLMC_FP16) s_tab16[i] = ((const __half*)prm.table)[i];
+            else if constexpr (PREC == MLMC_FP32) s_tab[i] = prescaled_coeff(((const float*)prm.table)[i], i % (DEG + 1));
             else s_tab[i] = ((const AT*)prm.table)[i];
             if constexpr (DIAG) s_tab64[i] = prm.table64[i];
         }

@@ -58,12 +58,11 @@ __device__ __forceinline__ float mlp_eval(float x, const float* __restrict__ W) 
 
 __device__ __forceinline__ float icdf_mlp_f32(uint32_t word, const float* __restrict__ W,
                                               const LogCell* __restrict__ logtab) {
-    const bool upper = (word >> 31) != 0;
-    const uint32_t xm = upper ? ~word : word;
+    const uint32_t xm = word ^ (uint32_t)((int32_t)word >> 31);  // ~word on the upper half
     const double r = mlp_radius(xm, logtab);
     const float x = (float)(r * (1.0 / 3.4) - 1.0);
     const float q = mlp_eval(x, W) - (float)r;
-    return upper ? -q : q;
+    return apply_sign(q, word & 0x80000000u);
 }
 
 }  // namespace mlmc
