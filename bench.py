@@ -32,12 +32,42 @@ sys.path.insert(0, ROOT)
 LEVELS = list(range(11))
 N_PATHS = 2 ** 20
 SEED = 0
-# VALU peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz, one full-rate VALU lane-operation
-# per lane per clock (= the binary64 vector peak 78.6 TFLOP/s / 2 flops per FMA)
+# VALU issue peak of MI355X in binary64-equivalent lane-operations: 256 CUs x 64 lanes x
+# 2.4 GHz (= the binary64 vector peak 78.6 TFLOP/s / 2 flops per FMA).  32-bit operations
+# (binary32, integer, logic) issue at twice that rate (the binary32 vector peak 157.3 TFLOP/s)
+# and weigh 1/2; the 32x32->64 integer product (v_mad_u64_u32) weighs 2 (measured).
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
-# algorithmic VALU lane-operations per coupled path-step of the nested binary32
-# piecewise-linear kernel with Kahan updates (operation list in the design doc)
-ALG_OPS_PER_STEP = 82.0
+# algorithmic binary64-equivalent VALU lane-operations per coupled path-step of the nested
+# binary32 piecewise-linear kernel with Kahan updates, for the minimal operation sequence of
+# this formulation:
+#   Philox4x32-10, a quarter call: 4 products x 2 + 4.5 three-input xors x 1/2     10.25
+#   exact inverse CDF: 38 binary64 operations (x, y = 1 - x^2, table log with a
+#     degree-3 log1p, degree-22 polynomial, tail test, x g) + 2 32-bit ones x 1/2  39.0
+#   binary64 fine and half coarse EM update: 5 + 6/2                               8.0
+#   piecewise-linear inverse CDF, binary32: 13 32-bit operations x 1/2             6.5
+#   binary32 fine and half coarse Kahan EM update: (8 + 9/2) x 1/2                 6.25
+ALG_OPS_PER_STEP = 70.0
+# HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+# (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
+TRAFFIC_BYTES_PER_LAUNCH = (97.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "63ce388fa8660c4ca4182299d4eb6d14fc98cbc00f82ef3cea65f613e9d9f507"
+KERNEL_SOURCES = ("level_kernel.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip", "icdf_exact_coeffs.h")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2012_09739_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    """The counter-derived traffic if the kernel sources are unchanged since it was taken."""
+    if TRAFFIC_BYTES_PER_LAUNCH is None or kernel_sources_sha256() != TRAFFIC_SOURCES_SHA256:
+        return None
+    return TRAFFIC_BYTES_PER_LAUNCH
 
 
 def parse():
@@ -58,7 +88,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU kernel; "
-              "paths shard across GPUs by path_offset (see DESIGN.md) but no multi-GPU run is made",
+              "paths shard across GPUs by path_offset but no multi-GPU run is made",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -142,8 +172,9 @@ def main():
                                "Kahan off and on",
                    "levels": LEVELS, "paths_per_level": N_PATHS, "kahan": [0, 1],
                    "coupled_path_steps_per_step": steps_per_pass, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS,
+                     "unit": "T binary64-equivalent VALU lane-ops/s",
+                     "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic_bytes(),
                      "kernel": "level_kernel<FP32, PWL16, nested, kahan> at level 10 (2^20 paths x 1024 steps)",
                      "kernel_ms": kern_ms, "alg_ops_per_path_step": ALG_OPS_PER_STEP},
         "cpu_baseline": cpu,
