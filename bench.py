@@ -91,6 +91,9 @@ def main():
               "paths shard across GPUs by path_offset but no multi-GPU run is made",
               file=sys.stderr)
         sys.exit(2)
+    # the CPU oracle runs first, in worker processes started before anything touches the GPU
+    cpu = None if a.no_cpu_baseline else cpu_baseline()
+
     import torch
 
     import paper_2012_09739_amd as M
@@ -150,8 +153,6 @@ def main():
 
     if not a.no_reports:
         extra["reports"] = reports(M, E, torch)
-
-    cpu = None if a.no_cpu_baseline else cpu_baseline()
 
     line = {
         "metric": "coupled path-steps/s FP16/FP32 vs FP64 at equal MLMC variance; % VALU peak",
@@ -300,13 +301,23 @@ def reports(M, E, torch):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
-        _, n_tasks = M.mlmc_batch_info(plan)
+        cfg, n_tasks = M.mlmc_batch_info(plan)
+        wave_s = M.mlmc_batch_item_times(plan, len(items))
     finally:
         M.mlmc_batch_destroy(plan)
     steps = sum(it.n_paths << it.level for it in items)
-    rep["batch_64psets_levels0to14"] = {"items": len(items), "tasks": n_tasks, "ms_per_sweep": ms,
-                                        "path_steps": steps, "path_steps_per_s": steps / ms * 1e3,
-                                        "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level]}
+    resident = cfg.waves_per_cu * torch.cuda.get_device_properties(0).multi_processor_count
+    # device time attributed to items in proportion to their wavefront time; cost per sample
+    share = [w / sum(wave_s) * ms * 1e-3 for w in wave_s]
+    per_level = {}
+    for it, c in zip(items, share):
+        per_level.setdefault(it.level, []).append(c / it.n_paths)
+    rep["batch_64psets_levels0to14"] = {
+        "items": len(items), "tasks": n_tasks, "ms_per_sweep": ms, "path_steps": steps,
+        "path_steps_per_s": steps / ms * 1e3,
+        "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level],
+        "wave_slot_utilisation": sum(wave_s) / (resident * ms * 1e-3),
+        "cost_per_sample_s_by_level": [float(np.mean(per_level[l])) for l in sorted(per_level)]}
 
     # learned inverse CDF: train on 2^20 pairs, nested four-way levels 0..10 at 2^22 paths vs PWL16
     params = torch.tensor(W.mlp_initial_params(0), dtype=torch.float32, device="cuda")
@@ -333,24 +344,46 @@ def reports(M, E, torch):
     return rep
 
 
-def cpu_baseline():
-    """The CPU oracle (float64 NumPy, one thread) on a bounded sample of the same workload:
-    Kahan variant, levels 0..10, 2^16 paths per level (1/32 of the GPU pass)."""
-    import numpy as np  # noqa: F401
+CPU_SINGLE_PATHS = 2 ** 15     # paths per level, one process
+CPU_POOL_PATHS = 2 ** 19       # paths per level over the worker pool
+CPU_TASK_PATHS = 2 ** 15       # paths per worker task
+CPU_MAX_WORKERS = 16           # the host share of one GPU
 
+
+def _oracle_task(task):
+    """One bounded piece of the CPU baseline: oracle level sums over a path range."""
     import mlmc_workloads as W
     from oracle import fp, mlmc
-    n = 2 ** 16
+    level, offset, n = task
+    mlmc.level_sums(level, n, W.GBM_CALL, path_offset=offset, rv_mode=mlmc.RV_PWL, precision=fp.FP32,
+                    nested=True, kahan=True, seed=SEED, stream=1)
+    return n * 2 ** level
+
+
+def cpu_baseline():
+    """The CPU oracle (float64 NumPy with binary32 emulation) on bounded samples of the
+    same workload (nested binary32 PWL16 with Kahan, levels 0..10): one process on
+    CPU_SINGLE_PATHS paths per level, then a pool of worker processes (at most the 16
+    cores of one GPU's host share) on CPU_POOL_PATHS paths per level."""
+    import multiprocessing as mp
+
     t0 = time.perf_counter()
-    steps = 0
-    for l in LEVELS:
-        mlmc.level_sums(l, n, W.GBM_CALL, rv_mode=mlmc.RV_PWL, precision=fp.FP32, nested=True, kahan=True,
-                        seed=SEED, stream=1)
-        steps += n * 2 ** l
-    dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "coupled path-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "nested binary32 PWL16 with Kahan, levels 0..10, 2^16 paths/level (%d coupled "
-                      "path-steps, %.1f s), single-threaded NumPy" % (steps, dt)}
+    steps1 = sum(_oracle_task((l, 0, CPU_SINGLE_PATHS)) for l in LEVELS)
+    dt1 = time.perf_counter() - t0
+
+    workers = max(1, min(CPU_MAX_WORKERS, os.cpu_count() or 1))
+    tasks = [(l, off, CPU_TASK_PATHS) for l in reversed(LEVELS) for off in range(0, CPU_POOL_PATHS, CPU_TASK_PATHS)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_task, [(0, 0, 64)] * workers, chunksize=1)  # start-up and imports, untimed
+        t0 = time.perf_counter()
+        steps = sum(pool.imap_unordered(_oracle_task, tasks, chunksize=1))
+        dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "coupled path-steps/s", "cores": workers, "kind": "oracle",
+            "single_core_value": steps1 / dt1,
+            "sample": "nested binary32 PWL16 with Kahan, levels 0..10: %d worker processes on 2^%d paths/level "
+                      "(%d coupled path-steps, %.1f s) and one process on 2^%d paths/level (%d, %.1f s); "
+                      "NumPy oracle" % (workers, CPU_POOL_PATHS.bit_length() - 1, steps, dt,
+                                        CPU_SINGLE_PATHS.bit_length() - 1, steps1, dt1)}
 
 
 if __name__ == "__main__":

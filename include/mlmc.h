@@ -229,6 +229,13 @@ int mlmc_batch_run_eager(mlmc_batch_t* plan, void* hip_stream);
  * cache when unset).  best: host, may be NULL.  Synchronous; d_out is overwritten. */
 int mlmc_batch_autotune(mlmc_batch_t* plan, int repeats, mlmc_batch_cfg_t* best);
 
+/* Cost of each item in the plan's last run (Section 3's c_l, per item): h_wave_seconds
+ * (host, n_items doubles) receives the wall-clock time that wavefronts spent on the item's
+ * tasks, summed over wavefronts (the device's constant-rate counter, read at the start and
+ * end of every task).  Dividing by the sum over items and multiplying by the sweep time
+ * attributes the device time to items.  Synchronous: waits for hip_stream first. */
+int mlmc_batch_item_times(mlmc_batch_t* plan, double* h_wave_seconds, void* hip_stream);
+
 /* The plan's current launch shape and task count (host outputs, either may be NULL). */
 int mlmc_batch_info(const mlmc_batch_t* plan, mlmc_batch_cfg_t* cfg, uint64_t* n_tasks);
 

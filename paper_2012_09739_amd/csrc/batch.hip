@@ -39,6 +39,7 @@ struct mlmc_batch {
     double* d_partials = nullptr;
     uint4* d_tasks = nullptr;
     uint32_t* d_counter = nullptr;
+    unsigned long long* d_ticks = nullptr;  // per item: wall-clock ticks summed over its tasks
     uint64_t n_tasks = 0;
     uint64_t task_capacity = 0;
     const void* tab32 = nullptr;
@@ -58,15 +59,20 @@ __host__ __device__ inline int variant_of(int precision, int kahan) {
     return (precision == MLMC_FP16 ? 0 : 2) + (kahan ? 1 : 0);
 }
 
-__global__ void queue_reset(uint32_t* counter) {
-    if (threadIdx.x == 0) counter[0] = 0u;
+// Clears the queue counter and the per-item tick sums (a kernel, not a memset, so that the
+// captured graph holds no memset node).
+__global__ void batch_reset(uint32_t* counter, unsigned long long* ticks, uint32_t n_items) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) counter[0] = 0u;
+    for (uint32_t k = i; k < n_items; k += gridDim.x * blockDim.x) ticks[k] = 0ull;
 }
 
 template <int RV>
-__global__ __launch_bounds__(256) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
                                                     const uint4* __restrict__ tasks, uint32_t n_tasks,
                                                     uint32_t* __restrict__ counter, const float* __restrict__ tab32,
-                                                    const __half* __restrict__ tab16, const LogCell* __restrict__ logtab) {
+                                                    const __half* __restrict__ tab16, const LogCell* __restrict__ logtab,
+                                                    unsigned long long* __restrict__ ticks) {
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
     __shared__ float s_tab32[kTableRows * 4];
     __shared__ __half s_tab16[kTableRows * 4];
@@ -87,14 +93,23 @@ __global__ __launch_bounds__(256) void batch_kernel(const LevelParams* __restric
         const LevelParams& prm = params[task.x];
         const int var = variant[task.x];
         if (task.w) __builtin_amdgcn_s_setprio(3);
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        // levels 0 and 1 (fewer than 4 steps) take the per-word exact variable
+        const int v = var + (prm.n_steps < 4 ? 4 : 0);
         for (uint32_t c = task.y; c < task.y + task.z; ++c) {
-            switch (var) {
+            switch (v) {
                 case 0: run_chunk<MLMC_FP16, RV, true, false, false>(prm, c, lane, s_tab16, nullptr, s_log); break;
                 case 1: run_chunk<MLMC_FP16, RV, true, true, false>(prm, c, lane, s_tab16, nullptr, s_log); break;
                 case 2: run_chunk<MLMC_FP32, RV, true, false, false>(prm, c, lane, s_tab32, nullptr, s_log); break;
-                default: run_chunk<MLMC_FP32, RV, true, true, false>(prm, c, lane, s_tab32, nullptr, s_log); break;
+                case 3: run_chunk<MLMC_FP32, RV, true, true, false>(prm, c, lane, s_tab32, nullptr, s_log); break;
+                case 4: run_chunk<MLMC_FP16, RV, true, false, false, true>(prm, c, lane, s_tab16, nullptr, s_log); break;
+                case 5: run_chunk<MLMC_FP16, RV, true, true, false, true>(prm, c, lane, s_tab16, nullptr, s_log); break;
+                case 6: run_chunk<MLMC_FP32, RV, true, false, false, true>(prm, c, lane, s_tab32, nullptr, s_log); break;
+                default: run_chunk<MLMC_FP32, RV, true, true, false, true>(prm, c, lane, s_tab32, nullptr, s_log); break;
             }
         }
+        const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+        if (lane == 0) atomicAdd(&ticks[task.x], (unsigned long long)(t1 - t0));
         if (task.w) __builtin_amdgcn_s_setprio(0);
     }
 }
@@ -196,17 +211,19 @@ std::vector<uint4> build_tasks(const mlmc_batch& b, const std::vector<uint64_t>&
 
 int enqueue(mlmc_batch* b, hipStream_t s) {
     const int blocks = std::max(1, b->n_cu * b->cfg.waves_per_cu / 4);
-    hipLaunchKernelGGL(queue_reset, dim3(1), dim3(64), 0, s, b->d_counter);
+    const uint32_t n_items = (uint32_t)b->items.size();
+    hipLaunchKernelGGL(batch_reset, dim3(std::min<uint32_t>(64, (n_items + 255) / 256)), dim3(256), 0, s, b->d_counter,
+                       b->d_ticks, n_items);
     int rc = hipck(hipGetLastError(), "queue reset launch");
     if (rc) return rc;
     if (b->rv == MLMC_RV_CUBIC16)
         hipLaunchKernelGGL(batch_kernel<MLMC_RV_CUBIC16>, dim3(blocks), dim3(256), 0, s, b->d_params, b->d_variant,
                            b->d_tasks, (uint32_t)b->n_tasks, b->d_counter, (const float*)b->tab32,
-                           (const __half*)b->tab16, (const LogCell*)b->logtab);
+                           (const __half*)b->tab16, (const LogCell*)b->logtab, b->d_ticks);
     else
         hipLaunchKernelGGL(batch_kernel<MLMC_RV_PWL16>, dim3(blocks), dim3(256), 0, s, b->d_params, b->d_variant,
                            b->d_tasks, (uint32_t)b->n_tasks, b->d_counter, (const float*)b->tab32,
-                           (const __half*)b->tab16, (const LogCell*)b->logtab);
+                           (const __half*)b->tab16, (const LogCell*)b->logtab, b->d_ticks);
     rc = hipck(hipGetLastError(), "batch kernel launch");
     if (rc) return rc;
     hipLaunchKernelGGL(batch_reduce, dim3((unsigned)b->items.size()), dim3(kReduceBlock), 0, s, b->d_partials,
@@ -258,7 +275,7 @@ int prepare(mlmc_batch* b) {
 void free_plan(mlmc_batch* b) {
     drop_graph(b);
     for (void* p : {(void*)b->d_params, (void*)b->d_variant, (void*)b->d_row_off, (void*)b->d_rows,
-                    (void*)b->d_partials, (void*)b->d_tasks, (void*)b->d_counter})
+                    (void*)b->d_partials, (void*)b->d_tasks, (void*)b->d_counter, (void*)b->d_ticks})
         if (p) (void)hipFree(p);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
@@ -336,6 +353,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
     alloc((void**)&b->d_rows, sizeof(uint64_t) * n_items, "hipMalloc rows");
     alloc((void**)&b->d_partials, sizeof(double) * kPartial * total_rows, "hipMalloc partials");
     alloc((void**)&b->d_counter, sizeof(uint32_t) * 64, "hipMalloc counter");
+    alloc((void**)&b->d_ticks, sizeof(unsigned long long) * n_items, "hipMalloc item ticks");
     if (!rc) rc = hipck(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     if (rc) {
         free_plan(b);
@@ -371,6 +389,23 @@ int mlmc_batch_run_eager(mlmc_batch_t* plan, void* hip_stream) {
     return enqueue(plan, (hipStream_t)hip_stream);
 }
 
+int mlmc_batch_item_times(mlmc_batch_t* plan, double* h_wave_seconds, void* hip_stream) {
+    if (!plan) return set_error(MLMC_EINVAL, "plan is NULL");
+    if (!h_wave_seconds) return set_error(MLMC_EINVAL, "h_wave_seconds is NULL");
+    int rc = hipck(hipStreamSynchronize((hipStream_t)hip_stream), "hipStreamSynchronize");
+    if (rc) return rc;
+    int khz = 0;
+    if ((rc = hipck(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, plan->device), "wall clock rate")))
+        return rc;
+    if (khz <= 0) return set_error(MLMC_EHIP, "device reports no wall clock rate");
+    std::vector<unsigned long long> t(plan->items.size());
+    if ((rc = hipck(hipMemcpy(t.data(), plan->d_ticks, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost),
+                    "hipMemcpy item ticks")))
+        return rc;
+    for (size_t i = 0; i < t.size(); ++i) h_wave_seconds[i] = (double)t[i] / (1e3 * khz);
+    return MLMC_OK;
+}
+
 int mlmc_batch_info(const mlmc_batch_t* plan, mlmc_batch_cfg_t* cfg, uint64_t* n_tasks) {
     if (!plan) return set_error(MLMC_EINVAL, "plan is NULL");
     if (cfg) *cfg = plan->cfg;
@@ -388,8 +423,25 @@ int mlmc_batch_autotune(mlmc_batch_t* plan, int repeats, mlmc_batch_cfg_t* best)
         (void)hipEventDestroy(e0);
         return rc;
     }
-    const int waves[] = {8, 16, 32};
-    const int steps[] = {256, 1024, 4096};
+    // wavefronts per CU: multiples of the 4-wave block up to what the kernel's register use
+    // lets reside at once (a persistent wave that cannot start before the queue drains is idle)
+    int blocks_per_cu = 0;
+    if (plan->rv == MLMC_RV_CUBIC16)
+        rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, batch_kernel<MLMC_RV_CUBIC16>, 256, 0),
+                   "occupancy query");
+    else
+        rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, batch_kernel<MLMC_RV_PWL16>, 256, 0),
+                   "occupancy query");
+    if (rc) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return rc;
+    }
+    std::vector<int> waves;
+    for (int w = 8; w <= 32; w += 4)
+        if (w <= 4 * blocks_per_cu) waves.push_back(w);
+    if (waves.empty()) waves.push_back(4 * std::max(1, blocks_per_cu));
+    const int steps[] = {64, 128, 256, 1024};
     const int prios[] = {10, 12, 25};
     mlmc_batch_cfg_t winner = plan->cfg;
     float best_ms = 1e30f;

@@ -91,7 +91,7 @@ __device__ __forceinline__ double icdf_exact_f64(uint32_t word, const LogCell* _
     if (w <= MLMC_ICDF_W1) {
         double acc = kCentral[MLMC_ICDF_CENTRAL_DEG];
 #pragma unroll
-        for (int i = MLMC_ICDF_CENTRAL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, w, kCentral[i]);
+        for (int i = MLMC_ICDF_CENTRAL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, w, sgpr_const(kCentral[i]));
         g = acc;
     } else {
         g = icdf_tail_g(w);

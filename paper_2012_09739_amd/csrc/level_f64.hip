@@ -6,6 +6,12 @@ namespace mlmc {
 namespace {
 template <int RV, bool NESTED, bool KAHAN, bool DIAG>
 hipError_t go(const LevelParams& p, int grid, int block, hipStream_t s) {
+    if constexpr (NESTED || RV == MLMC_RV_EXACT) {
+        if (p.n_steps < 4) {
+            hipLaunchKernelGGL((level_kernel<MLMC_FP64, RV, NESTED, KAHAN, DIAG, true>), dim3(grid), dim3(block), 0, s, p);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((level_kernel<MLMC_FP64, RV, NESTED, KAHAN, DIAG>), dim3(grid), dim3(block), 0, s, p);
     return hipGetLastError();
 }

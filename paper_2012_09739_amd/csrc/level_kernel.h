@@ -99,7 +99,7 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
 // level and writes the chunk's 8 partial sums to prm.partials[chunk].  s_tab is the
 // coefficient table in the working precision (binary32: prescaled, see prescaled_coeff) and
 // s_tab64 the binary64 one (diagnostic), both in LDS.
-template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG>
+template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false>
 __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
                                           const double* s_tab64, const LogCell* s_log) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
@@ -151,8 +151,17 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
         for (int l = 0; l < L; ++l) r[l] = philox4x32_10(q, path[l], prm.ctr2, prm.pset, prm.key0, prm.key1);
         double zx[L][4];
         if constexpr (kNeedExact) {
+            if constexpr (!SHORT) {
 #pragma unroll
-            for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], s_log, kc);
+                for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], s_log, kc);
+            } else {
+                // levels 0 and 1 use only the first one or two words of the call
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    zx[l][0] = icdf_exact_f64(r[l].w[0], s_log);
+                    zx[l][1] = prm.n_steps > 1 ? icdf_exact_f64(r[l].w[1], s_log) : 0.0;
+                }
+            }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -277,7 +286,8 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
     }
 }
 
-template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG>
+// SHORT: the instance for levels with fewer than 4 fine steps (exact variables one word at a time).
+template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false>
 __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
@@ -316,7 +326,7 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
     constexpr uint32_t kChunk = kWave * L;
     const uint64_t n_chunks = (prm.n_paths + kChunk - 1) / kChunk;
     for (uint64_t chunk = wave; chunk < n_chunks; chunk += n_waves)
-        run_chunk<PREC, RV, NESTED, KAHAN, DIAG>(prm, chunk, lane, tab, s_tab64, s_log);
+        run_chunk<PREC, RV, NESTED, KAHAN, DIAG, SHORT>(prm, chunk, lane, tab, s_tab64, s_log);
 }
 
 }  // namespace mlmc

@@ -86,6 +86,7 @@ _SIGNATURES = {
     "mlmc_batch_run_eager": (ctypes.c_int, [_P, _P]),
     "mlmc_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(mlmc_batch_cfg_t)]),
     "mlmc_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(mlmc_batch_cfg_t), ctypes.POINTER(ctypes.c_uint64)]),
+    "mlmc_batch_item_times": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), _P]),
     "mlmc_batch_destroy": (ctypes.c_int, [_P]),
     "mlmc_mlp_pairs": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _P, _P, _P, _P]),
     "mlmc_mlp_grad": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _P, _P, _P]),
@@ -240,6 +241,13 @@ def mlmc_batch_info(plan):
     n = ctypes.c_uint64()
     _check(lib().mlmc_batch_info(plan, ctypes.byref(cfg), ctypes.byref(n)))
     return cfg, n.value
+
+
+def mlmc_batch_item_times(plan, n_items, stream=None):
+    """Wavefront-seconds spent on each of the plan's n_items items in its last run."""
+    buf = (ctypes.c_double * n_items)()
+    _check(lib().mlmc_batch_item_times(plan, buf, _stream(stream)))
+    return list(buf)
 
 
 def mlmc_batch_destroy(plan):

@@ -164,3 +164,37 @@ def test_invalid_items_rejected():
     with pytest.raises(M.MlmcError) as e:
         M.mlmc_batch_create([bad], M.MLMC_RV_PWL16, out)
     assert e.value.code == M.MLMC_EINVAL
+
+
+def test_item_times_account_for_the_sweep():
+    """Per-item wavefront time (cost attribution, Section 3's c_l per item): positive, not
+    accumulated across replays, bounded by resident waves x elapsed time, and proportional
+    to the work within one arithmetic variant."""
+    torch = torch_cuda()
+    psets = W.batch_parameter_sets(8, seed=4)
+    items, meta = make_items(psets, W.BATCH_LEVELS, W.batch_paths)
+    out = torch.zeros((len(items), 8), dtype=torch.float64, device="cuda")
+    plan = M.mlmc_batch_create(items, M.MLMC_RV_PWL16, out)
+    try:
+        cfg, _ = M.mlmc_batch_info(plan)
+        waves = cfg.waves_per_cu * torch.cuda.get_device_properties(0).multi_processor_count
+        totals = []
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            M.mlmc_batch_run(plan)
+            e1.record()
+            torch.cuda.synchronize()
+            t = np.array(M.mlmc_batch_item_times(plan, len(items)))
+            elapsed = e0.elapsed_time(e1) * 1e-3
+            assert np.all(t > 0)
+            assert t.sum() <= waves * elapsed * 1.05, (t.sum(), waves, elapsed)
+            totals.append(t.sum())
+    finally:
+        M.mlmc_batch_destroy(plan)
+    assert 0.5 < totals[1] / totals[0] < 2.0   # reset on every replay, not accumulated
+    steps = np.array([it.n_paths << it.level for it in items], dtype=np.float64)
+    per = t / steps
+    fp32 = np.array([m[1] >= 9 for m in meta])   # binary32 items with whole 64-path chunks busy
+    ratio = per[fp32].max() / per[fp32].min()
+    assert ratio < 4.0, ratio
