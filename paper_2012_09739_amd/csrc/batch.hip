@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void b
     }
 }
 
-__global__ __launch_bounds__(kReduceBlock) void batch_reduce(const double* __restrict__ partials,
+__global__ __launch_bounds__(kReduceBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void batch_reduce(const double* __restrict__ partials,
                                                              const uint64_t* __restrict__ row_off,
                                                              const uint64_t* __restrict__ rows, double* __restrict__ out) {
     __shared__ double s[kPartial][kReduceBlock];

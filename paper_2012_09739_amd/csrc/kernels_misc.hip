@@ -15,7 +15,7 @@ namespace {
 // t, t + 256, ... sequentially, then a fixed tree over the 256 threads.  The order depends
 // only on n_chunks, so results do not depend on the level kernel's launch shape, and the
 // batched sweep (one block per item) reproduces the single-level sums bit for bit.
-__global__ __launch_bounds__(kReduceBlock) void reduce_chunks(const double* __restrict__ partials,
+__global__ __launch_bounds__(kReduceBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void reduce_chunks(const double* __restrict__ partials,
                                                               uint64_t n_chunks, double* __restrict__ out) {
     __shared__ double s[kPartial][kReduceBlock];
     reduce_rows_block(partials, n_chunks, out, s);

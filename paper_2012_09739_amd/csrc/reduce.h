@@ -16,7 +16,22 @@ __device__ __forceinline__ void reduce_rows_block(const double* __restrict__ row
     double acc[kPartial];
 #pragma unroll
     for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
-    for (uint64_t c = threadIdx.x; c < n; c += kReduceBlock) {
+    // thread t adds rows t, t + B, t + 2B, ... in that order; the loads of kAhead rows are
+    // issued before their additions so the loop is not bound by one memory latency per row
+    constexpr int kAhead = 16;
+    uint64_t c = threadIdx.x;
+    for (; c + (uint64_t)(kAhead - 1) * kReduceBlock < n; c += (uint64_t)kAhead * kReduceBlock) {
+        double v[kAhead][kPartial];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+#pragma unroll
+            for (int k = 0; k < kPartial; ++k) v[u][k] = rows[(c + (uint64_t)u * kReduceBlock) * kPartial + k];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+#pragma unroll
+            for (int k = 0; k < kPartial; ++k) acc[k] += v[u][k];
+    }
+    for (; c < n; c += kReduceBlock) {
 #pragma unroll
         for (int k = 0; k < kPartial; ++k) acc[k] += rows[c * kPartial + k];
     }
