@@ -340,6 +340,19 @@ def reports(M, E, torch):
                                "pwl16": float(((zs[M.MLMC_RV_PWL16] - zs[M.MLMC_RV_EXACT]) ** 2).mean())},
         "four_way_var": {"mlp": var(mlp_rows, 1), "pwl16": var(pwl_rows, 1)},
         "nested_path_steps_per_s": {"mlp": rate(mlp_rows), "pwl16": rate(pwl_rows)}}
+    # adaptive MLMC with a per-level precision map from measured costs, against the plain
+    # binary64 estimator at the same accuracy (call payoff, eps = 1e-5)
+    from paper_2012_09739_amd import driver as D
+    mixed = D.adaptive_mlmc(call, 1e-5, seed=21)
+    plain = D.adaptive_mlmc(call, 1e-5, options=(D.PLAIN_FP64,), seed=21)
+    rep["adaptive_mlmc_call_eps1e-5"] = {
+        "estimate": mixed["estimate"], "std_error": mixed["std_error"], "L": mixed["L"],
+        "choice": mixed["choice"], "predicted_speedup_vs_fp64": mixed["predicted_seconds_single_option"]["fp64"]
+        / mixed["predicted_seconds"],
+        "measured_device_seconds": mixed["measured_seconds"],
+        "plain_fp64_estimate": plain["estimate"], "plain_fp64_std_error": plain["std_error"],
+        "plain_fp64_measured_device_seconds": plain["measured_seconds"],
+        "measured_speedup_vs_fp64": plain["measured_seconds"] / mixed["measured_seconds"]}
     np.seterr(all="ignore")
     return rep
 

@@ -1,0 +1,198 @@
+"""Adaptive MLMC with a per-level precision map chosen from measured device costs.
+
+Section 3 writes each level correction of the nested estimator as an approximate two-way
+difference plus a four-way correction; a level may instead use the plain exact two-way
+difference.  Every option has the same expectation E[P^_l - P^_{l-1}] (the four-way term
+removes the approximation's bias exactly), so any per-level mixture of options is an
+unbiased estimator of E[P^_L].  With optimal sample counts the cost of reaching mean
+squared error eps^2 (variance eps^2 / 2, bias at most eps / sqrt 2) is
+
+    T = 2 eps^-2 (sum_l a_l)^2,   a_l = sqrt(v^_l c^_l)                      (plain)
+                                  a_l = sqrt(v-_l c-_l) + sqrt(V-_l C-_l)      (nested)
+
+(Section 3's T^ and T-), so the cheapest mixture takes at every level the option with the
+smallest a_l.  The number of samples of each term j is m_j = 2 eps^-2 sqrt(v_j / c_j)
+sum_k sqrt(v_k c_k) over all terms of all levels.
+
+Levels are added until Giles' weak-error test holds: with alpha = 1 (Euler-Maruyama),
+max(|E d_L|, |E d_{L-1}| / 2) / (2^alpha - 1) <= eps / sqrt 2, d_l the exact two-way
+difference.  Every sample comes from the level calls of the C-ABI; the arithmetic here
+is on a few numbers per level.  Pilot and final samples use different Philox keys.
+"""
+
+import math
+from dataclasses import dataclass, field
+
+from . import mlmc as M
+from .estimators import level_stats
+
+ALPHA = 1.0  # weak order of Euler-Maruyama
+
+
+@dataclass(frozen=True)
+class Option:
+    """One way of sampling a level correction."""
+    name: str
+    precision: int          # MLMC_FP64 (plain, exact variables) or the approximate pair's
+    rv: int = M.MLMC_RV_EXACT
+    kahan: int = 0
+
+    @property
+    def nested(self):
+        return self.rv != M.MLMC_RV_EXACT
+
+
+PLAIN_FP64 = Option("fp64", M.MLMC_FP64)
+NESTED_FP32 = Option("fp32-pwl", M.MLMC_FP32, M.MLMC_RV_PWL16, 0)
+NESTED_FP32_KAHAN = Option("fp32-pwl-kahan", M.MLMC_FP32, M.MLMC_RV_PWL16, 1)
+NESTED_FP16_KAHAN = Option("fp16-cubic-kahan", M.MLMC_FP16, M.MLMC_RV_CUBIC16, 1)
+DEFAULT_OPTIONS = (PLAIN_FP64, NESTED_FP32, NESTED_FP32_KAHAN, NESTED_FP16_KAHAN)
+
+
+@dataclass
+class LevelPilot:
+    """Pilot statistics of one level: per option the variances and costs per sample of its
+    terms (plain: [(v^, c^)]; nested: [(v-, c-), (V-, C-)]) and the exact two-way mean."""
+    level: int
+    terms: dict = field(default_factory=dict)
+    mean_exact: float = 0.0
+
+
+# ---- pure arithmetic (CPU-testable) ---------------------------------------------------------
+
+def cost_weight(terms):
+    """a_l of an option: sum over its terms of sqrt(v c)."""
+    return math.fsum(math.sqrt(v * c) for v, c in terms)
+
+
+def choose(pilot):
+    """Name of the option with the smallest a_l at this level."""
+    return min(pilot.terms, key=lambda k: cost_weight(pilot.terms[k]))
+
+
+def allocate(terms, eps):
+    """Optimal sample counts for a flat list of (v, c) terms at mean squared error eps^2."""
+    total = math.fsum(math.sqrt(v * c) for v, c in terms)
+    return [max(2, math.ceil(2.0 / eps ** 2 * math.sqrt(v / c) * total)) for v, c in terms]
+
+
+def predicted_time(terms, eps):
+    """T = 2 eps^-2 (sum sqrt(v c))^2 for a flat list of (v, c) terms."""
+    return 2.0 / eps ** 2 * math.fsum(math.sqrt(v * c) for v, c in terms) ** 2
+
+
+def weak_converged(means, eps, alpha=ALPHA):
+    """Giles' test on the exact two-way means of levels 0..L (needs L >= 2)."""
+    if len(means) < 3:
+        return False
+    rem = max(abs(means[-1]), abs(means[-2]) / 2.0 ** alpha) / (2.0 ** alpha - 1.0)
+    return rem <= eps / math.sqrt(2.0)
+
+
+# ---- sampling through the C-ABI ------------------------------------------------------------
+
+def _stats(r, term):
+    mean, var = level_stats(r["sum"][term], r["sumsq"][term], r["n_paths"])
+    return mean, var
+
+
+def _marginal(call, n):
+    """Run n and then 2n samples; returns the 2n-sample result and the device time per extra
+    sample (t(2n) - t(n)) / n, which leaves out the fixed cost of a call (launch, reduction)."""
+    r1 = call(n)
+    r2 = call(2 * n)
+    extra = r2["cost_seconds"] - r1["cost_seconds"]
+    return r2, max(extra, 0.05 * r2["cost_seconds"]) / n
+
+
+def pilot_level(sde, level, options, n, seed):
+    """Pilot runs of every option at one level: variances from 2n samples, device costs per
+    sample as marginal costs (after a warm call, so that no first-launch cost enters)."""
+    p = LevelPilot(level)
+    for opt in options:
+        if not opt.nested:
+            M.mlmc_level(sde, level, 1024, opt.precision, M.MLMC_EXACT, 0, seed)
+            r, c = _marginal(lambda k: M.mlmc_level(sde, level, k, opt.precision, M.MLMC_EXACT, 0, seed), n)
+            m, v = _stats(r, 0)
+            p.terms[opt.name] = [(v, c)]
+            p.mean_exact = m
+        else:
+            approx, nested = opt.rv, opt.rv + 4
+            M.mlmc_level(sde, level, 1024, opt.precision, approx, opt.kahan, seed)
+            M.mlmc_level(sde, level, 1024, opt.precision, nested, opt.kahan, seed)
+            r, c = _marginal(lambda k: M.mlmc_level(sde, level, k, opt.precision, approx, opt.kahan, seed), n)
+            _, v = _stats(r, 0)
+            r, C = _marginal(lambda k: M.mlmc_level(sde, level, k, opt.precision, nested, opt.kahan, seed), n)
+            _, V = _stats(r, 1)
+            p.terms[opt.name] = [(v, c), (V, C)]
+            if not any(not o.nested for o in options):
+                p.mean_exact = _stats(r, 2)[0]
+    return p
+
+
+def _run_term(sde, level, opt, term_index, n, seed):
+    """n samples of one term of one option; returns (sum, sum of squares, n, device seconds)."""
+    if not opt.nested:
+        r = M.mlmc_level(sde, level, n, opt.precision, M.MLMC_EXACT, 0, seed)
+        t = 0
+    elif term_index == 0:
+        r = M.mlmc_level(sde, level, n, opt.precision, opt.rv, opt.kahan, seed)
+        t = 0
+    else:
+        r = M.mlmc_level(sde, level, n, opt.precision, opt.rv + 4, opt.kahan, seed)
+        t = 1
+    return r["sum"][t], r["sumsq"][t], n, r["cost_seconds"]
+
+
+def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pilot=2 ** 19, seed=0,
+                  max_samples=2 ** 32):
+    """Adaptive MLMC to root-mean-square error eps with a per-level choice among options.
+
+    Returns a dict: estimate, its standard error, L, per-level choice, samples per term,
+    the predicted device time of the chosen mixture and of each single option used at every
+    level (the plain binary64 estimator among them), and the measured device time of the
+    final sampling (pilot runs excluded; each call also pays a fixed launch and reduction
+    cost of some 20 us that the per-sample model leaves out)."""
+    by_name = {o.name: o for o in options}
+    pilots = []
+    level = 0
+    while True:
+        pilots.append(pilot_level(sde, level, options, n_pilot, seed))
+        if level >= l_min and weak_converged([p.mean_exact for p in pilots], eps):
+            break
+        if level == l_max:
+            break
+        level += 1
+    L = level
+    choice = [choose(p) for p in pilots]
+    flat, where = [], []
+    for l, (p, name) in enumerate(zip(pilots, choice)):
+        for j, vc in enumerate(p.terms[name]):
+            flat.append(vc)
+            where.append((l, name, j))
+    counts = allocate(flat, eps)
+    if max(counts) > max_samples:
+        raise ValueError("eps too small for max_samples")
+    final_seed = seed + 1
+    sums = {}
+    device_s = 0.0
+    for (l, name, j), n in zip(where, counts):
+        s, q, m, t = _run_term(sde, l, by_name[name], j, n, final_seed)
+        sums[(l, j)] = (s, q, m)
+        device_s += t
+    estimate, var = 0.0, 0.0
+    parts = []
+    for (l, j), (s, q, m) in sorted(sums.items()):
+        mean, v = level_stats(s, q, m)
+        parts.append(mean)
+        var += v / m
+    estimate = math.fsum(parts)
+    single = {}
+    for o in options:
+        terms = [vc for p in pilots for vc in p.terms[o.name]]
+        single[o.name] = predicted_time(terms, eps)
+    return {"estimate": estimate, "std_error": math.sqrt(var), "L": L, "choice": choice,
+            "samples": {"%d/%s/%d" % w: n for w, n in zip(where, counts)},
+            "predicted_seconds": predicted_time(flat, eps), "predicted_seconds_single_option": single,
+            "measured_seconds": device_s,
+            "per_level_a": [{k: cost_weight(v) for k, v in p.terms.items()} for p in pilots]}

@@ -1,0 +1,91 @@
+"""Host logic of the adaptive MLMC driver (per-level option choice, optimal allocation,
+weak-error test), with a synthetic sampler standing in for the level calls: its sums are
+exact functions of prescribed means, variances and costs, so the driver's arithmetic can be
+checked against closed forms without a GPU."""
+
+import math
+
+import pytest
+
+import paper_2012_09739_amd as M
+from paper_2012_09739_amd import driver as D
+
+
+def test_allocate_meets_the_variance_target_at_the_predicted_cost():
+    terms = [(0.04, 1e-9), (4e-4, 2e-9), (2e-4, 4e-9), (1e-5, 3e-9), (1e-7, 8e-9)]
+    eps = 1e-3
+    m = D.allocate(terms, eps)
+    var = math.fsum(v / n for (v, _), n in zip(terms, m))
+    cost = math.fsum(c * n for (_, c), n in zip(terms, m))
+    assert var <= eps ** 2 / 2 * (1 + 1e-12)
+    assert var >= eps ** 2 / 2 * 0.999          # ceil only rounds counts up slightly
+    assert cost == pytest.approx(D.predicted_time(terms, eps), rel=1e-3)
+    # Lagrange: m_j = ceil(K s_j) with s_j = sqrt(v_j / c_j) and one K for all terms
+    s_j = [math.sqrt(v / c) for v, c in terms]
+    K = 2.0 / eps ** 2 * math.fsum(math.sqrt(v * c) for v, c in terms)
+    assert all(K * sj <= n < K * sj + 1 for sj, n in zip(s_j, m))
+
+
+def test_choice_takes_the_smallest_cost_weight():
+    p = D.LevelPilot(3, terms={"a": [(1e-4, 4e-9)], "b": [(1e-4, 1e-9), (1e-8, 4e-9)], "c": [(1e-3, 1e-9)]})
+    assert D.cost_weight(p.terms["b"]) == pytest.approx(math.sqrt(1e-13) + math.sqrt(4e-17))
+    assert D.choose(p) == "b"
+
+
+@pytest.mark.parametrize("K,eps,L_expected", [(1e-2, 1e-3, 4), (1e-2, 1e-4, 8)])
+def test_weak_error_test(K, eps, L_expected):
+    # means d_l = K 2^-l: converged at the first L >= 2 with K 2^-L <= eps / sqrt 2
+    L = next(L for L in range(2, 40) if D.weak_converged([K * 2.0 ** -l for l in range(L + 1)], eps))
+    assert L == L_expected
+    assert K * 2.0 ** -L <= eps / math.sqrt(2) < K * 2.0 ** -(L - 1)
+
+
+class FakeLevels:
+    """Stands in for mlmc_level: sums of n samples equal n * mean and the sums of squares
+    n * (var + mean^2), so level_stats returns the prescribed mean and (n/(n-1)) var."""
+
+    def __init__(self, mu=0.05):
+        self.calls = []
+        self.mu = mu
+
+    def moments(self, level, precision, mode):
+        d = 1e-2 * 2.0 ** -level
+        v_exact = 0.04 if level == 0 else 1e-3 * 2.0 ** -level
+        base = {M.MLMC_FP64: 8e-9, M.MLMC_FP32: 2e-9, M.MLMC_FP16: 1e-9}[precision] * 2 ** level
+        if mode == M.MLMC_EXACT:
+            return [(d, v_exact)], base
+        approx = mode in (M.MLMC_RV_PWL16, M.MLMC_RV_CUBIC16)
+        if approx:
+            return [(d * 0.99, v_exact)], base
+        return [(d * 0.99, v_exact), (d * 0.01, 1e-8 * 2.0 ** -level), (d, v_exact)], base + 8e-9 * 2 ** level
+
+    def __call__(self, sde, level, n, precision, mode, kahan, seed):
+        self.calls.append((level, n, precision, mode, kahan, seed))
+        terms, c = self.moments(level, precision, mode)
+        s, q = [math.nan] * 4, [math.nan] * 4
+        for k, (mean, var) in enumerate(terms):
+            s[k] = n * mean
+            q[k] = n * (var + mean * mean)
+        return {"sum": s, "sumsq": q, "n_paths": n, "path_steps": n << level, "cost_seconds": c * n}
+
+
+def test_driver_orchestration_with_synthetic_levels(monkeypatch):
+    fake = FakeLevels()
+    monkeypatch.setattr(D.M, "mlmc_level", fake)
+    eps = 1e-3
+    out = D.adaptive_mlmc(None, eps, n_pilot=1 << 16)
+    L = out["L"]
+    assert L == 4                                     # 1e-2 2^-L <= eps / sqrt 2
+    # the estimate is the sum of the prescribed level means whatever the choice per level
+    assert out["estimate"] == pytest.approx(math.fsum(1e-2 * 2.0 ** -l for l in range(L + 1)), rel=1e-12)
+    # every level's choice minimises a_l, and the mixture is never predicted slower than a
+    # single option used at every level
+    for l, name in enumerate(out["choice"]):
+        a = out["per_level_a"][l]
+        assert a[name] == min(a.values())
+    assert out["predicted_seconds"] <= min(out["predicted_seconds_single_option"].values()) * (1 + 1e-12)
+    # with these costs the nested binary16 option wins at every level and the plain one loses
+    assert set(out["choice"]) == {"fp16-cubic-kahan"}
+    # pilot and final samples use different Philox keys
+    assert {c[-1] for c in fake.calls} == {0, 1}
+    assert out["std_error"] <= eps / math.sqrt(2) * 1.01
