@@ -41,12 +41,13 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 # binary32 piecewise-linear kernel with Kahan updates, for the minimal operation sequence of
 # this formulation:
 #   Philox4x32-10, a quarter call: 4 products x 2 + 4.5 three-input xors x 1/2     10.25
-#   exact inverse CDF: 38 binary64 operations (x, y = 1 - x^2, table log with a
-#     degree-3 log1p, degree-22 polynomial, tail test, x g) + 2 32-bit ones x 1/2  39.0
+#   exact inverse CDF: 26 binary64 operations (x, y = 1 - x^2, table log with a
+#     degree-3 log1p, interval and coordinate of g, degree-7 piece, x g) + 4
+#     32-bit ones x 1/2                                                            28.0
 #   binary64 fine and half coarse EM update: 5 + 6/2                               8.0
 #   piecewise-linear inverse CDF, binary32: 13 32-bit operations x 1/2             6.5
 #   binary32 fine and half coarse Kahan EM update: (8 + 9/2) x 1/2                 6.25
-ALG_OPS_PER_STEP = 70.0
+ALG_OPS_PER_STEP = 59.0
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
 TRAFFIC_BYTES_PER_LAUNCH = (97.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md

@@ -82,7 +82,7 @@ struct DevState {
     size_t scratch_bytes = 0;
     double* out8 = nullptr;             // result slot of the synchronous entry point
     float* mlp = nullptr;               // MLP inference image (binary16 values as binary32)
-    double* logtab = nullptr;           // 256 cells (f, -log f) of the table-driven log
+    void* exact_tab = nullptr;          // ExactTable: log cells and piecewise coefficients of g
     bool mlp_loaded = false;
 };
 
@@ -152,16 +152,20 @@ int device_state(DevState** out) {
         if ((e = hipMalloc(&st.mlp, kMlpImage * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
         {
             // cell i covers the frexp mantissa m in [(1 + i/256)/2, (1 + (i+1)/256)/2):
-            // f = R(1/c), l = R(-log f), c the centre
-            double h[2 * kLogCells];
+            // f = R(1/c), l = R(-log f), c the centre; then the generated piecewise
+            // coefficients of g, coefficient-major
+            static ExactTable h;
             for (int i = 0; i < kLogCells; ++i) {
                 const double c = 0.5 + (i + 0.5) / (2.0 * kLogCells);
                 const double f = 1.0 / c;
-                h[2 * i] = f;
-                h[2 * i + 1] = (double)(-std::log((long double)f));
+                h.log[i].f = f;
+                h.log[i].l = (double)(-std::log((long double)f));
             }
-            if ((e = hipMalloc(&st.logtab, sizeof h)) != hipSuccess) return hip_fail(e, "hipMalloc");
-            if ((e = hipMemcpy(st.logtab, h, sizeof h, hipMemcpyHostToDevice)) != hipSuccess)
+            static const double kPiece[] = MLMC_ICDF_PIECE_COEFFS;
+            static_assert(sizeof kPiece == sizeof h.piece, "piecewise table size");
+            std::memcpy(h.piece, kPiece, sizeof kPiece);
+            if ((e = hipMalloc(&st.exact_tab, sizeof h)) != hipSuccess) return hip_fail(e, "hipMalloc");
+            if ((e = hipMemcpy(st.exact_tab, &h, sizeof h, hipMemcpyHostToDevice)) != hipSuccess)
                 return hip_fail(e, "hipMemcpy");
         }
         rc = upload_tables(st);
@@ -259,7 +263,7 @@ LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevS
         p.table64 = st.tables64[r];
     }
     p.mlp = st.mlp;
-    p.logtab = st.logtab;
+    p.exact_tab = st.exact_tab;
     p.partials = partials;
     return p;
 }
@@ -358,7 +362,7 @@ int device_info(DeviceInfo* out) {
     }
     out->mlp = st->mlp;
     out->mlp_loaded = st->mlp_loaded;
-    out->logtab = st->logtab;
+    out->exact_tab = st->exact_tab;
     return MLMC_OK;
 }
 
@@ -396,7 +400,7 @@ int mlmc_shutdown(void) {
         if (st.scratch) (void)hipFree(st.scratch);
         if (st.out8) (void)hipFree(st.out8);
         if (st.mlp) (void)hipFree(st.mlp);
-        if (st.logtab) (void)hipFree(st.logtab);
+        if (st.exact_tab) (void)hipFree(st.exact_tab);
         if (st.ev0) (void)hipEventDestroy(st.ev0);
         if (st.ev1) (void)hipEventDestroy(st.ev1);
         if (st.stream) (void)hipStreamDestroy(st.stream);
@@ -523,7 +527,7 @@ int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double
     if (n == 0) return MLMC_OK;
     const void* table = nullptr;
     if (rv == MLMC_RV_PWL16 || rv == MLMC_RV_CUBIC16) table = st->tables[rv == MLMC_RV_PWL16 ? 0 : 1][precision];
-    hipError_t e = launch_icdf(d_words, n, rv, precision, table, st->mlp, st->logtab, d_out,
+    hipError_t e = launch_icdf(d_words, n, rv, precision, table, st->mlp, st->exact_tab, d_out,
                                (hipStream_t)hip_stream);
     return e == hipSuccess ? MLMC_OK : hip_fail(e, "icdf kernel launch");
 }

@@ -44,7 +44,7 @@ struct mlmc_batch {
     uint64_t task_capacity = 0;
     const void* tab32 = nullptr;
     const void* tab16 = nullptr;
-    const void* logtab = nullptr;
+    const void* exact_tab = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -71,17 +71,18 @@ template <int RV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
                                                     const uint4* __restrict__ tasks, uint32_t n_tasks,
                                                     uint32_t* __restrict__ counter, const float* __restrict__ tab32,
-                                                    const __half* __restrict__ tab16, const LogCell* __restrict__ logtab,
+                                                    const __half* __restrict__ tab16, const void* __restrict__ exact_tab,
                                                     unsigned long long* __restrict__ ticks) {
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
     __shared__ float s_tab32[kTableRows * 4];
     __shared__ __half s_tab16[kTableRows * 4];
-    __shared__ LogCell s_log[kLogCells];
+    __shared__ __align__(16) unsigned char s_ex_raw[sizeof(ExactTable)];
+    const ExactTable* s_ex = (const ExactTable*)s_ex_raw;
     for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
         s_tab32[i] = prescaled_coeff(tab32[i], i % (DEG + 1));
         s_tab16[i] = tab16[i];
     }
-    for (int i = threadIdx.x; i < kLogCells; i += blockDim.x) s_log[i] = logtab[i];
+    stage_exact_table(s_ex_raw, exact_tab);
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
     for (;;) {
@@ -98,14 +99,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void b
         const int v = var + (prm.n_steps < 4 ? 4 : 0);
         for (uint32_t c = task.y; c < task.y + task.z; ++c) {
             switch (v) {
-                case 0: run_chunk<MLMC_FP16, RV, true, false, false>(prm, c, lane, s_tab16, nullptr, s_log); break;
-                case 1: run_chunk<MLMC_FP16, RV, true, true, false>(prm, c, lane, s_tab16, nullptr, s_log); break;
-                case 2: run_chunk<MLMC_FP32, RV, true, false, false>(prm, c, lane, s_tab32, nullptr, s_log); break;
-                case 3: run_chunk<MLMC_FP32, RV, true, true, false>(prm, c, lane, s_tab32, nullptr, s_log); break;
-                case 4: run_chunk<MLMC_FP16, RV, true, false, false, true>(prm, c, lane, s_tab16, nullptr, s_log); break;
-                case 5: run_chunk<MLMC_FP16, RV, true, true, false, true>(prm, c, lane, s_tab16, nullptr, s_log); break;
-                case 6: run_chunk<MLMC_FP32, RV, true, false, false, true>(prm, c, lane, s_tab32, nullptr, s_log); break;
-                default: run_chunk<MLMC_FP32, RV, true, true, false, true>(prm, c, lane, s_tab32, nullptr, s_log); break;
+                case 0: run_chunk<MLMC_FP16, RV, true, false, false>(prm, c, lane, s_tab16, nullptr, s_ex); break;
+                case 1: run_chunk<MLMC_FP16, RV, true, true, false>(prm, c, lane, s_tab16, nullptr, s_ex); break;
+                case 2: run_chunk<MLMC_FP32, RV, true, false, false>(prm, c, lane, s_tab32, nullptr, s_ex); break;
+                case 3: run_chunk<MLMC_FP32, RV, true, true, false>(prm, c, lane, s_tab32, nullptr, s_ex); break;
+                case 4: run_chunk<MLMC_FP16, RV, true, false, false, true>(prm, c, lane, s_tab16, nullptr, s_ex); break;
+                case 5: run_chunk<MLMC_FP16, RV, true, true, false, true>(prm, c, lane, s_tab16, nullptr, s_ex); break;
+                case 6: run_chunk<MLMC_FP32, RV, true, false, false, true>(prm, c, lane, s_tab32, nullptr, s_ex); break;
+                default: run_chunk<MLMC_FP32, RV, true, true, false, true>(prm, c, lane, s_tab32, nullptr, s_ex); break;
             }
         }
         const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
@@ -219,11 +220,11 @@ int enqueue(mlmc_batch* b, hipStream_t s) {
     if (b->rv == MLMC_RV_CUBIC16)
         hipLaunchKernelGGL(batch_kernel<MLMC_RV_CUBIC16>, dim3(blocks), dim3(256), 0, s, b->d_params, b->d_variant,
                            b->d_tasks, (uint32_t)b->n_tasks, b->d_counter, (const float*)b->tab32,
-                           (const __half*)b->tab16, (const LogCell*)b->logtab, b->d_ticks);
+                           (const __half*)b->tab16, b->exact_tab, b->d_ticks);
     else
         hipLaunchKernelGGL(batch_kernel<MLMC_RV_PWL16>, dim3(blocks), dim3(256), 0, s, b->d_params, b->d_variant,
                            b->d_tasks, (uint32_t)b->n_tasks, b->d_counter, (const float*)b->tab32,
-                           (const __half*)b->tab16, (const LogCell*)b->logtab, b->d_ticks);
+                           (const __half*)b->tab16, b->exact_tab, b->d_ticks);
     rc = hipck(hipGetLastError(), "batch kernel launch");
     if (rc) return rc;
     hipLaunchKernelGGL(batch_reduce, dim3((unsigned)b->items.size()), dim3(kReduceBlock), 0, s, b->d_partials,
@@ -330,7 +331,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
     const int r = rv == MLMC_RV_PWL16 ? 0 : 1;
     b->tab32 = di.tables[r][MLMC_FP32];
     b->tab16 = di.tables[r][MLMC_FP16];
-    b->logtab = di.logtab;
+    b->exact_tab = di.exact_tab;
 
     std::vector<LevelParams> prm(n_items);
     std::vector<int> var(n_items);
@@ -364,7 +365,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
         fill_level_params(&prm[i], it.sde, it.level, it.precision, it.n_paths, 0, it.seed, it.stream, it.pset);
         prm[i].partials = b->d_partials + off[i] * kPartial;
         prm[i].mlp = di.mlp;
-        prm[i].logtab = di.logtab;
+        prm[i].exact_tab = di.exact_tab;
     }
     if (!rc) rc = hipck(hipMemcpy(b->d_params, prm.data(), sizeof(LevelParams) * n_items, hipMemcpyHostToDevice), "copy");
     if (!rc) rc = hipck(hipMemcpy(b->d_variant, var.data(), sizeof(int) * n_items, hipMemcpyHostToDevice), "copy");

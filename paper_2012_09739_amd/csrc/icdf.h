@@ -4,9 +4,10 @@
 // Z~ = Phi~^{-1}(U) through the same uniform U; here U = (x + 1/2) 2^-32 for a word x.
 //
 // Exact (binary64): Phi^{-1}(u) = x g(w) with x = 2u - 1 and w = -log((1 - x)(1 + x)),
-// g an entire function of w evaluated by one polynomial in w on w <= 6 (99.88% of words;
-// fewer than one wavefront in ten sees a tail word in a given slot) and by one in sqrt(w)
-// beyond; -log is table driven (256 cells, the table in LDS or global memory).
+// g an entire function of w.  -log is table driven (256 cells) and g is piecewise: on each
+// of 86 intervals of width 1/4 covering every w of a 32-bit word, one polynomial of
+// degree 7 in the local coordinate, its coefficients read per lane from the same table (in
+// LDS or global memory), so every lane runs the same instructions whatever its interval.
 // x is exact and y = 1 - x^2 = (1 - x)(1 + x) is rounded once (one fma); the result is
 // exactly odd under word -> 2^32 - 1 - word.
 //
@@ -55,24 +56,24 @@ __device__ __forceinline__ double neg_log_f64(double y, const LogCell* __restric
     return -__builtin_fma(kd, kLn2, log_m);
 }
 
-// Places a binary64 constant in an SGPR pair at its point of use.  The polynomial
-// coefficients are then scalar operands of v_fma_f64 (one instruction per Horner step)
-// instead of loop-invariant VGPR copies that cost a v_mov per step and occupancy.
+// Places a binary64 constant in an SGPR pair at its point of use, as the scalar operand of
+// a v_fma_f64, instead of a loop-invariant VGPR copy that costs a v_mov and occupancy.
 __device__ __forceinline__ double sgpr_const(double c) {
     asm volatile("" : "+s"(c));
     return c;
 }
 
-// g(w) on the tail w > 6 (about one word in eight hundred): out of line so that its
-// coefficients are materialised only when a lane needs them.
-__device__ __noinline__ double icdf_tail_g(double w) {
-    constexpr double kTail[] = MLMC_ICDF_TAIL_COEFFS;
-    double acc = kTail[MLMC_ICDF_TAIL_DEG];
-    const double d = __builtin_sqrt(w) - MLMC_ICDF_MID2;
-#pragma unroll
-    for (int i = MLMC_ICDF_TAIL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, d, sgpr_const(kTail[i]));
-    return acc;
-}
+// Table of the exact variable: the log cells and, interval-major, the piecewise
+// coefficients of g (piece[k][j] is coefficient j of interval k: one 64-byte row per
+// interval, read with four 16-byte loads from one address).
+constexpr int kPieces = MLMC_ICDF_PIECES;
+constexpr int kPieceDeg = MLMC_ICDF_PIECE_DEG;
+static_assert(kPieceDeg == 7, "one 64-byte row of 8 coefficients per interval");
+struct ExactTable {
+    LogCell log[kLogCells];
+    double piece[kPieces][kPieceDeg + 1];
+};
+static_assert(sizeof(ExactTable) % 16 == 0, "staged in 16-byte pieces");
 
 // x = 2u - 1 = word 2^-31 + (2^-32 - 1), exact in binary64 (a multiple of 2^-32 below 1 in
 // magnitude), and y = (1 - x)(1 + x) = 1 - x^2 rounded once.
@@ -83,20 +84,24 @@ __device__ __forceinline__ double icdf_y(double x) {
     return __builtin_fma(-x, x, 1.0);
 }
 
-__device__ __forceinline__ double icdf_exact_f64(uint32_t word, const LogCell* __restrict__ tab) {
-    const double x = icdf_x(word);
-    const double w = neg_log_f64(icdf_y(x), tab);
-    constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
-    double g;
-    if (w <= MLMC_ICDF_W1) {
-        double acc = kCentral[MLMC_ICDF_CENTRAL_DEG];
+// g(w): interval k = floor(4 |w|) and local coordinate f = 4 |w| - k, both exact.  w is
+// below 0 only by a rounding when y rounds to 1 (|x| < 2^-26.5), where g(|w|) = g(0) to
+// far below binary64 resolution; the absolute value is a free source modifier.
+__device__ __forceinline__ double icdf_g(double w, const double (*__restrict__ piece)[kPieceDeg + 1]) {
+    const double t = __builtin_fabs(w) * (double)MLMC_ICDF_PIECE_SCALE;
+    const uint32_t k0 = (uint32_t)(int)t;
+    const uint32_t k = k0 < (uint32_t)(kPieces - 1) ? k0 : (uint32_t)(kPieces - 1);
+    const double f = __builtin_amdgcn_fract(t);
+    const double* c = piece[k];
+    double acc = c[kPieceDeg];
 #pragma unroll
-        for (int i = MLMC_ICDF_CENTRAL_DEG - 1; i >= 0; --i) acc = __builtin_fma(acc, w, sgpr_const(kCentral[i]));
-        g = acc;
-    } else {
-        g = icdf_tail_g(w);
-    }
-    return x * g;
+    for (int j = kPieceDeg - 1; j >= 0; --j) acc = __builtin_fma(acc, f, c[j]);
+    return acc;
+}
+
+__device__ __forceinline__ double icdf_exact_f64(uint32_t word, const ExactTable* __restrict__ tab) {
+    const double x = icdf_x(word);
+    return x * icdf_g(neg_log_f64(icdf_y(x), tab->log), tab->piece);
 }
 
 // Binary64 constants held in VGPRs for a whole chunk.  Each is an operand of an fma whose
@@ -105,49 +110,32 @@ __device__ __forceinline__ double icdf_exact_f64(uint32_t word, const LogCell* _
 struct ExactConsts {
     double x0;     // 2^-32 - 1, the addend of x = word 2^-31 + x0
     double p_top;  // leading log1p coefficient
-    double g_top;  // leading central coefficient
 };
 
 __device__ __forceinline__ ExactConsts exact_consts() {
     constexpr double kP[] = MLMC_LOG1P_COEFFS;
-    constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
-    ExactConsts k{0x1p-32 - 1.0, kP[MLMC_LOG1P_DEG], kCentral[MLMC_ICDF_CENTRAL_DEG]};
-    asm volatile("" : "+v"(k.x0), "+v"(k.p_top), "+v"(k.g_top));
+    ExactConsts k{0x1p-32 - 1.0, kP[MLMC_LOG1P_DEG]};
+    asm volatile("" : "+v"(k.x0), "+v"(k.p_top));
     return k;
 }
 
-// Exact variables of four words at once: the four Horner chains share every
-// coefficient (one scalar materialisation per coefficient for four FMAs) and give the
-// scheduler four independent dependency chains.
+// Exact variables of four words at once (four independent chains for the scheduler).
 __device__ __forceinline__ void icdf_exact_f64x4(const uint32_t (&word)[4], double (&z)[4],
-                                                 const LogCell* __restrict__ tab, const ExactConsts& kc) {
-    constexpr double kCentral[] = MLMC_ICDF_CENTRAL_COEFFS;
-    double x[4], w[4], acc[4];
+                                                 const ExactTable* __restrict__ tab, const ExactConsts& kc) {
+    double x[4], w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         x[k] = __builtin_fma((double)word[k], sgpr_const(0x1p-31), kc.x0);
-        w[k] = neg_log_f64(icdf_y(x[k]), tab, kc.p_top, true);
+        w[k] = neg_log_f64(icdf_y(x[k]), tab->log, kc.p_top, true);
     }
-    {
-        const double c = sgpr_const(kCentral[MLMC_ICDF_CENTRAL_DEG - 1]);
+    // one word's coefficient row at a time: each result is pinned before the next row is
+    // read (the asm takes the result as an operand and clobbers memory), so at most one
+    // row of 8 coefficients (16 VGPRs) is live instead of all of them
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = __builtin_fma(kc.g_top, w[k], c);
+    for (int k = 0; k < 4; ++k) {
+        z[k] = x[k] * icdf_g(w[k], tab->piece);
+        asm volatile("" : "+v"(z[k])::"memory");
     }
-#pragma unroll
-    for (int i = MLMC_ICDF_CENTRAL_DEG - 2; i >= 0; --i) {
-        const double c = sgpr_const(kCentral[i]);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = __builtin_fma(acc[k], w[k], c);
-    }
-    // one comparison for the four words; the per-word tests run only when some lane of
-    // the wavefront has a tail word
-    if (__builtin_fmax(__builtin_fmax(w[0], w[1]), __builtin_fmax(w[2], w[3])) > MLMC_ICDF_W1) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (w[k] > MLMC_ICDF_W1) acc[k] = icdf_tail_g(w[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) z[k] = x[k] * acc[k];
 }
 
 // Interval j-1 (0-based row of the table), mirror flag and the local coordinate scaled to

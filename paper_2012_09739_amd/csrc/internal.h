@@ -36,7 +36,7 @@ struct LevelParams {
     const void* table;     // 16 x (DEG + 1) coefficients in the working precision
     const double* table64; // 16 x (DEG + 1) binary64 master coefficients (diagnostic)
     const void* mlp;       // MLP inference image (rv = MLP)
-    const void* logtab;    // cells of the table-driven binary64 log (exact inverse CDF)
+    const void* exact_tab; // ExactTable: log cells and piecewise coefficients (exact inverse CDF)
     double* partials;      // [n_chunks][kPartial] chunk partial sums
     // optional per-path outputs (device, n_paths entries each, may be null)
     double* out_pf_hat;
@@ -61,7 +61,7 @@ hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* d_ou
 hipError_t launch_uniforms(uint64_t seed, uint32_t ctr2, uint32_t pset, uint64_t path0,
                            uint64_t n_paths, uint32_t n_steps, uint32_t* d_words, hipStream_t s);
 hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, const void* table,
-                       const void* mlp, const void* logtab, double* d_out, hipStream_t s);
+                       const void* mlp, const void* exact_tab, double* d_out, hipStream_t s);
 
 // Device resources the library keeps for the current device (lazily initialised).
 struct DeviceInfo {
@@ -70,7 +70,7 @@ struct DeviceInfo {
     const double* tables64[2];
     const void* mlp;
     bool mlp_loaded;
-    const void* logtab;
+    const void* exact_tab;
 };
 int device_info(DeviceInfo* out);
 int set_error(int code, const char* fmt, ...);

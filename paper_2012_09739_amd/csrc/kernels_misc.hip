@@ -40,16 +40,16 @@ __global__ void uniforms_kernel(uint32_t k0, uint32_t k1, uint32_t ctr2, uint32_
 
 template <int RV, int PREC>
 __global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, const void* table,
-                            const void* mlp, const LogCell* __restrict__ logtab, double* __restrict__ out) {
+                            const void* mlp, const ExactTable* __restrict__ ex, double* __restrict__ out) {
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
          g += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t w = words[g];
         double z;
         if constexpr (RV == MLMC_RV_EXACT) {
-            z = icdf_exact_f64(w, logtab);
+            z = icdf_exact_f64(w, ex);
         } else if constexpr (RV == MLMC_RV_MLP) {
-            const float y = icdf_mlp_f32(w, (const float*)mlp, logtab);
+            const float y = icdf_mlp_f32(w, (const float*)mlp, ex->log);
             if constexpr (PREC == MLMC_FP16) z = (double)__half2float(__float2half_rn(y));
             else z = (double)y;
         } else if constexpr (PREC == MLMC_FP64) {
@@ -84,16 +84,16 @@ hipError_t launch_uniforms(uint64_t seed, uint32_t ctr2, uint32_t pset, uint64_t
 }
 
 hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, const void* table,
-                       const void* mlp, const void* logtab_v, double* d_out, hipStream_t s) {
-    const LogCell* logtab = (const LogCell*)logtab_v;
+                       const void* mlp, const void* exact_tab, double* d_out, hipStream_t s) {
+    const ExactTable* ex = (const ExactTable*)exact_tab;
     const dim3 g(grid_for(n, 256)), b(256);
 #define MLMC_ICDF_CASE(R, P) \
     if (rv == R && precision == P) { \
-        hipLaunchKernelGGL((icdf_kernel<R, P>), g, b, 0, s, d_words, n, table, mlp, logtab, d_out); \
+        hipLaunchKernelGGL((icdf_kernel<R, P>), g, b, 0, s, d_words, n, table, mlp, ex, d_out); \
         return hipGetLastError(); \
     }
     if (rv == MLMC_RV_EXACT) {
-        hipLaunchKernelGGL((icdf_kernel<MLMC_RV_EXACT, MLMC_FP64>), g, b, 0, s, d_words, n, table, mlp, logtab, d_out);
+        hipLaunchKernelGGL((icdf_kernel<MLMC_RV_EXACT, MLMC_FP64>), g, b, 0, s, d_words, n, table, mlp, ex, d_out);
         return hipGetLastError();
     }
     MLMC_ICDF_CASE(MLMC_RV_PWL16, MLMC_FP64)

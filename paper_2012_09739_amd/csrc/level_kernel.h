@@ -82,6 +82,13 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Copies the exact-variable table (log cells and piecewise coefficients) into LDS.
+__device__ __forceinline__ void stage_exact_table(unsigned char* dst, const void* src) {
+    const uint4* s = (const uint4*)src;
+    uint4* d = (uint4*)dst;
+    for (int i = threadIdx.x; i < (int)(sizeof(ExactTable) / 16); i += blockDim.x) d[i] = s[i];
+}
+
 // ---- the kernel ------------------------------------------------------------------------
 // Approximate variable of one word in the working precision (binary64 or binary32).
 template <int RV, int DEG, typename T>
@@ -101,7 +108,7 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
 // s_tab64 the binary64 one (diagnostic), both in LDS.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false>
 __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
-                                          const double* s_tab64, const LogCell* s_log) {
+                                          const double* s_tab64, const ExactTable* s_ex) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kExactOnly = (RV == MLMC_RV_EXACT);
     constexpr bool kNeedExact = kExactOnly || NESTED;
@@ -153,13 +160,13 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
         if constexpr (kNeedExact) {
             if constexpr (!SHORT) {
 #pragma unroll
-                for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], s_log, kc);
+                for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], s_ex, kc);
             } else {
                 // levels 0 and 1 use only the first one or two words of the call
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
-                    zx[l][0] = icdf_exact_f64(r[l].w[0], s_log);
-                    zx[l][1] = prm.n_steps > 1 ? icdf_exact_f64(r[l].w[1], s_log) : 0.0;
+                    zx[l][0] = icdf_exact_f64(r[l].w[0], s_ex);
+                    zx[l][1] = prm.n_steps > 1 ? icdf_exact_f64(r[l].w[1], s_ex) : 0.0;
                 }
             }
         }
@@ -177,7 +184,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
                 }
             }
             if constexpr (kNeedApprox && PREC != MLMC_FP16) {
-                const AT z = approx_rv<RV, DEG, AT>(r[0].w[i], s_tab, mlpw, s_log);
+                const AT z = approx_rv<RV, DEG, AT>(r[0].w[i], s_tab, mlpw, s_ex->log);
                 if constexpr (kKahan) {
                     em_step_kahan<AT>(Xfb, cfb, z, ca_b, cb_b);
                     if (coarse) em_step_kahan<AT>(Xcb, ccb, zb_prev + z, cac_b, cb_b);
@@ -190,8 +197,8 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
             if constexpr (kNeedApprox && PREC == MLMC_FP16) {
                 __half z0, z1;
                 if constexpr (RV == MLMC_RV_MLP) {
-                    z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw, s_log));
-                    z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw, s_log));
+                    z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw, s_ex->log));
+                    z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw, s_ex->log));
                 } else {
                     z0 = icdf_dyadic_f16<DEG>(r[0].w[i], s_tab16);
                     z1 = icdf_dyadic_f16<DEG>(r[1].w[i], s_tab16);
@@ -210,7 +217,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     double zt;
-                    if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw, s_log);
+                    if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw, s_ex->log);
                     else zt = icdf_dyadic_f64<DEG>(r[l].w[i], s_tab64);
                     em_step<double>(Xft[l], zt, prm.ca_f64, prm.cb_f64);
                 }
@@ -288,7 +295,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
 
 // SHORT: the instance for levels with fewer than 4 fine steps (exact variables one word at a time).
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false>
-__global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC != MLMC_FP16 && RV != MLMC_RV_MLP ? 7 : 1))) void level_kernel(const LevelParams prm) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
     constexpr int L = (PREC == MLMC_FP16) ? 2 : 1;
@@ -300,9 +307,10 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
     __shared__ double s_tab64[kTableRows * 4];
     __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
     constexpr bool kNeedLog = RV == MLMC_RV_EXACT || NESTED || RV == MLMC_RV_MLP;
-    __shared__ LogCell s_log[kNeedLog ? kLogCells : 1];
+    __shared__ __align__(16) unsigned char s_ex_raw[kNeedLog ? sizeof(ExactTable) : 16];
+    const ExactTable* s_ex = (const ExactTable*)s_ex_raw;
     if constexpr (kNeedLog) {
-        for (int i = threadIdx.x; i < kLogCells; i += blockDim.x) s_log[i] = ((const LogCell*)prm.logtab)[i];
+        stage_exact_table(s_ex_raw, prm.exact_tab);
         __syncthreads();
     }
     if constexpr (kDyadic) {
@@ -326,7 +334,7 @@ __global__ __launch_bounds__(256) void level_kernel(const LevelParams prm) {
     constexpr uint32_t kChunk = kWave * L;
     const uint64_t n_chunks = (prm.n_paths + kChunk - 1) / kChunk;
     for (uint64_t chunk = wave; chunk < n_chunks; chunk += n_waves)
-        run_chunk<PREC, RV, NESTED, KAHAN, DIAG, SHORT>(prm, chunk, lane, tab, s_tab64, s_log);
+        run_chunk<PREC, RV, NESTED, KAHAN, DIAG, SHORT>(prm, chunk, lane, tab, s_tab64, s_ex);
 }
 
 }  // namespace mlmc

@@ -33,13 +33,13 @@ __device__ __forceinline__ uint32_t pair_word(uint32_t i, uint32_t k0, uint32_t 
 }
 
 __global__ void pairs_kernel(uint32_t k0, uint32_t k1, uint32_t first, uint32_t n, uint32_t* __restrict__ words,
-                             float* __restrict__ xs, float* __restrict__ ts, const LogCell* __restrict__ logtab) {
+                             float* __restrict__ xs, float* __restrict__ ts, const ExactTable* __restrict__ ex) {
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
         const uint32_t xm = pair_word(first + g, k0, k1);
-        const double r = mlp_radius(xm, logtab);
+        const double r = mlp_radius(xm, ex->log);
         if (words) words[g] = xm;
         xs[g] = (float)(r * (1.0 / 3.4) - 1.0);
-        ts[g] = (float)(icdf_exact_f64(xm, logtab) + r);
+        ts[g] = (float)(icdf_exact_f64(xm, ex) + r);
     }
 }
 
@@ -206,7 +206,7 @@ int mlmc_mlp_pairs(uint64_t seed, uint32_t first, uint32_t n, uint32_t* d_words,
     if (rc || n == 0) return rc;
     const uint32_t grid = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
     hipLaunchKernelGGL(pairs_kernel, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream, (uint32_t)seed,
-                       (uint32_t)(seed >> 32), first, n, d_words, d_x, d_target, (const LogCell*)di.logtab);
+                       (uint32_t)(seed >> 32), first, n, d_words, d_x, d_target, (const ExactTable*)di.exact_tab);
     return ck(hipGetLastError(), "pairs kernel launch");
 }
 
@@ -226,7 +226,7 @@ int mlmc_mlp_grad(const float* d_params, uint64_t seed, uint32_t first, uint32_t
         return MLMC_ENOMEM;
     const uint32_t grid = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
     hipLaunchKernelGGL(pairs_kernel, dim3(grid), dim3(256), 0, s, (uint32_t)seed, (uint32_t)(seed >> 32), first, n,
-                       nullptr, (float*)xs.p, (float*)ts.p, (const LogCell*)di.logtab);
+                       nullptr, (float*)xs.p, (float*)ts.p, (const ExactTable*)di.exact_tab);
     hipLaunchKernelGGL(grad_kernel, dim3(blocks), dim3(kTB), 0, s, d_params, (const float*)xs.p, (const float*)ts.p,
                        0u, n, 1.0f / (float)n, (float*)bg.p);
     hipLaunchKernelGGL(reduce_grad_kernel, dim3(1), dim3(384), 0, s, (const float*)bg.p, blocks, d_grad, d_loss,
@@ -256,7 +256,7 @@ int mlmc_mlp_train(const mlmc_mlp_cfg_t* cfg, float* d_params, float* h_loss, vo
         return MLMC_ENOMEM;
     const uint32_t grid = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
     hipLaunchKernelGGL(pairs_kernel, dim3(grid), dim3(256), 0, s, (uint32_t)cfg->seed, (uint32_t)(cfg->seed >> 32),
-                       0u, n, nullptr, (float*)xs.p, (float*)ts.p, (const LogCell*)di.logtab);
+                       0u, n, nullptr, (float*)xs.p, (float*)ts.p, (const ExactTable*)di.exact_tab);
     hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(256), 0, s, (float*)st.p, (uint32_t)(2 * kMlpParams), 0.0f,
                        (uint32_t*)cnt.p);
     if ((rc = ck(hipGetLastError(), "training set-up launch"))) return rc;
