@@ -50,8 +50,8 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 ALG_OPS_PER_STEP = 59.0
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (97.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "63ce388fa8660c4ca4182299d4eb6d14fc98cbc00f82ef3cea65f613e9d9f507"
+TRAFFIC_BYTES_PER_LAUNCH = (89.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "2c24cb07275c4c92c9bd7897c2afc0ca2f150be01d269daf6a72892efc0f6417"
 KERNEL_SOURCES = ("level_kernel.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip", "icdf_exact_coeffs.h")
 
 
