@@ -8,7 +8,12 @@ rounding per operation:
 * float64 and float32 arithmetic in NumPy is IEEE correctly rounded;
 * float16 arithmetic in NumPy is computed in float32 and rounded to float16, which is the
   correctly rounded float16 result for + - x because 24 >= 2*11 + 2 (double rounding is
-  innocuous when the wider format has at least 2p+2 bits; Figueroa, 1995).
+  innocuous when the wider format has at least 2p+2 bits; Figueroa, 1995);
+* bfloat16 (8 significant bits, the exponent range of binary32; the 7-bit-mantissa format of
+  the precision experiments around Figure 3) has no NumPy dtype: values are held in float64
+  arrays of class ``BF16Array``, whose + - x max min round every result to 8 significant
+  bits (``round_bits``), the correctly rounded result since the float64 operation on two
+  8-bit operands is exact or at least 2*8+2 bits wide.
 
 Nothing here uses fused multiply-add: the method's operations are the separate roundings
 the paper writes.
@@ -16,16 +21,70 @@ the paper writes.
 
 import numpy as np
 
-FP64, FP32, FP16 = 0, 1, 2
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 DTYPES = {FP64: np.float64, FP32: np.float32, FP16: np.float16}
 # unit roundoff of each format (half the gap between 1 and the next representable number)
-UNIT_ROUNDOFF = {FP64: 2.0 ** -53, FP32: 2.0 ** -24, FP16: 2.0 ** -11}
+UNIT_ROUNDOFF = {FP64: 2.0 ** -53, FP32: 2.0 ** -24, FP16: 2.0 ** -11, BF16: 2.0 ** -8}
+
+
+def round_bits(x, p):
+    """Round finite float64 value(s) to p significant bits (2 <= p <= 52), to nearest with
+    ties to even, from the bit pattern: add half an ulp of the kept part (minus one unless
+    the kept part is odd) and clear the dropped bits; a carry into the exponent gives the
+    next binade exactly."""
+    x = np.asarray(x, dtype=np.float64)
+    u = x.view(np.uint64)
+    d = np.uint64(53 - p)
+    one = np.uint64(1)
+    lsb = (u >> d) & one
+    r = np.asarray((u + ((one << (d - one)) - one) + lsb) & ~((one << d) - one))
+    return r.view(np.float64)
+
+
+class BF16Array(np.ndarray):
+    """bfloat16 values held in float64: the listed ufuncs round their result to 8 bits."""
+
+    _ROUNDED = (np.add, np.subtract, np.multiply, np.maximum, np.minimum, np.negative, np.absolute)
+
+    def __array_ufunc__(self, ufunc, method, *inputs, **kwargs):
+        args = [a.view(np.ndarray) if isinstance(a, np.ndarray) else a for a in inputs]
+        res = getattr(ufunc, method)(*args, **kwargs)
+        if method == "__call__" and ufunc in self._ROUNDED:
+            return round_bits(res, 8).view(BF16Array)
+        return res
+
+
+def bf16(x):
+    """R_bf16(x) of float64 value(s) as a BF16Array (one correctly rounded conversion)."""
+    return round_bits(x, 8).view(BF16Array)
 
 
 def dtype(precision):
-    return DTYPES[precision]
+    """The constructor of values of precision p (a NumPy scalar type, or bf16)."""
+    return bf16 if precision == BF16 else DTYPES[precision]
 
 
 def rn(precision, x):
     """R_p(x): round float64 value(s) x to precision p (one correctly rounded conversion)."""
+    if precision == BF16:
+        return bf16(x)
     return np.asarray(x, dtype=np.float64).astype(DTYPES[precision])
+
+
+def full(value, n):
+    """n copies of a value of some precision, in that precision."""
+    if isinstance(value, BF16Array):
+        return np.full(n, float(value)).view(BF16Array)
+    return np.full(n, value, dtype=np.asarray(value).dtype)
+
+
+def like(ref, values):
+    """values (exactly representable in ref's precision) converted to ref's precision."""
+    if isinstance(ref, BF16Array):
+        return np.asarray(values, dtype=np.float64).view(BF16Array)
+    return np.asarray(values).astype(np.asarray(ref).dtype)
+
+
+def to64(x):
+    """Exact conversion to plain float64 (differences are formed in binary64)."""
+    return np.array(np.asarray(x, dtype=np.float64), dtype=np.float64, copy=True).view(np.ndarray)

@@ -70,8 +70,8 @@ def coefficients(rv_mode, precision):
 
 
 def local_coordinate(t, precision):
-    if precision == fp.FP16:
-        return fp.rn(fp.FP16, fp.rn(fp.FP32, t).astype(np.float64))
+    if precision in (fp.FP16, fp.BF16):   # formed in binary32 and narrowed
+        return fp.rn(precision, fp.rn(fp.FP32, t).astype(np.float64))
     return fp.rn(precision, t)
 
 
@@ -85,4 +85,4 @@ def approx(x, rv_mode, precision):
     for i in range(d - 1, -1, -1):
         q = q * tp          # one rounding
         q = q + c[..., i]   # one rounding
-    return np.where(s, -q, q)
+    return fp.like(q, np.where(s, -q, q))

@@ -88,12 +88,11 @@ def payoff(X, kind, K):
 def _paths(level, Z, Zc_sum, consts, kahan):
     """Fine and coarse terminal states of one path pair; Z has shape (paths, steps)."""
     ca_f, ca_c, cb, x0, _ = consts
-    dt = type(x0)
     n_paths, n_steps = Z.shape
-    Xf = np.full(n_paths, x0, dtype=dt)
-    Xc = np.full(n_paths, x0, dtype=dt)
-    cf = np.zeros(n_paths, dtype=dt) if kahan else None
-    cc = np.zeros(n_paths, dtype=dt) if kahan else None
+    Xf = fp.full(x0, n_paths)
+    Xc = fp.full(x0, n_paths)
+    cf = fp.full(x0 - x0, n_paths) if kahan else None
+    cc = fp.full(x0 - x0, n_paths) if kahan else None
     for n in range(n_steps):
         Xf, cf = em_update(Xf, Z[:, n], ca_f, cb, cf)
         if level >= 1 and n % 2 == 1:
@@ -141,10 +140,10 @@ def level_paths(level, paths, sde, *, rv_mode, precision, nested, kahan, seed,
         else:
             Zt = icdf.approx(w, rv_mode, precision)
         Xf, Xc = _paths(level, Zt, coarse_of(Zt), cp, kahan=kahan and precision != fp.FP64)
-        Pf = payoff(Xf, kind, cp[4]).astype(np.float64)
-        Pc = payoff(Xc, kind, cp[4]).astype(np.float64) if level >= 1 else np.zeros(paths.size)
+        Pf = fp.to64(payoff(Xf, kind, cp[4]))
+        Pc = fp.to64(payoff(Xc, kind, cp[4])) if level >= 1 else np.zeros(paths.size)
         out["Pf_bar"], out["Pc_bar"] = Pf, Pc
-        out["Xf_bar"] = Xf.astype(np.float64)
+        out["Xf_bar"] = fp.to64(Xf)
         two_bar = Pf - Pc
         terms[TERM_TWO_WAY] = two_bar
         if nested:
