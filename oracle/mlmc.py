@@ -19,6 +19,14 @@ Restates, one rounding per operation, what the GPU library computes for one MLMC
   (P^_l - P^_{l-1}) - (P-_l - P-_{l-1}); the exact pair is binary64 with exact variables,
   the approximate pair runs in precision p with approximate variables.  Differences are
   formed in binary64 from the payoffs (a low-precision payoff converts exactly).
+* Milstein variant (named in Section 2 among the usual schemes; Section 4 discusses its
+  order-1 strong convergence, which moves the MLMC work to the coarse levels).  For GBM,
+  b b' = sigma^2 X, and the scheme adds (1/2) sigma^2 X (dW^2 - delta) to the
+  Euler-Maruyama increment.  Reading (the paper gives no finite-precision form):
+  M = (cm (x) X) (x) (Z (x) Z (-) k) with cm = R_p(sigma^2 delta_f / 2) and
+  dX = (A (+) B) (+) M; on the fine path k = 1, on the coarse path Zc = Z_{2m} (+) Z_{2m+1}
+  is the coarse increment over sqrt(delta_f), so dW_c^2 - 2 delta_f = delta_f (Zc^2 - 2) and
+  the same cm serves with k = 2.  k is exact in every format.
 * Optional rounding diagnostic (Lemma 2.6): X-_N (precision p, approximate variables)
   minus X~_N (binary64 arithmetic with the same approximate variables evaluated in
   binary64), isolating the rounding error of the low-precision path.
@@ -36,18 +44,20 @@ from . import fp, icdf, philox
 from . import mlp as _mlp
 
 RV_EXACT, RV_PWL, RV_CUBIC, RV_MLP = 0, 1, 2, 3
+SCHEME_EM, SCHEME_MILSTEIN = 0, 1
 PAYOFF_X, PAYOFF_CALL = 0, 1
 TERM_TWO_WAY, TERM_FOUR_WAY, TERM_TWO_WAY_EXACT, TERM_ROUNDING = 0, 1, 2, 3
 
 
 def constants(sde, level, precision):
-    """(ca_f, ca_c, cb, x0, K) rounded once to precision p from binary64 values."""
+    """(ca_f, ca_c, cb, x0, K, cm) rounded once to precision p from binary64 values."""
     dt_f = float(sde["T"]) * 2.0 ** -level
     ca_f = sde["mu"] * dt_f
     ca_c = sde["mu"] * (2.0 * dt_f)
     cb = sde["sigma"] * math.sqrt(dt_f)
+    cm = 0.5 * sde["sigma"] * sde["sigma"] * dt_f
     d = fp.dtype(precision)
-    return (d(ca_f), d(ca_c), d(cb), d(sde["x0"]), d(sde.get("strike", 1.0)))
+    return (d(ca_f), d(ca_c), d(cb), d(sde["x0"]), d(sde.get("strike", 1.0)), d(cm))
 
 
 def kahan_add(a, x, c):
@@ -78,6 +88,18 @@ def em_update(X, Z, ca, cb, comp=None):
     return kahan_add(X, dX, comp)
 
 
+def milstein_update(X, Z, ca, cb, cm, k, comp=None):
+    """One Milstein state update for GBM in the dtype of X: dX = (A (+) B) (+) M with
+    M = (cm (x) X) (x) (Z (x) Z (-) k); k = 1 on the fine path, 2 on the coarse path."""
+    A = ca * X
+    B = (cb * X) * Z
+    M = (cm * X) * (Z * Z - k)
+    dX = (A + B) + M
+    if comp is None:
+        return X + dX, None
+    return kahan_add(X, dX, comp)
+
+
 def payoff(X, kind, K):
     """P(X) in the dtype of X: X itself, or the call max(X (-) K, 0)."""
     if kind == PAYOFF_X:
@@ -85,23 +107,30 @@ def payoff(X, kind, K):
     return np.maximum(X - K, np.zeros_like(X))
 
 
-def _paths(level, Z, Zc_sum, consts, kahan):
+def _paths(level, Z, Zc_sum, consts, kahan, scheme=SCHEME_EM):
     """Fine and coarse terminal states of one path pair; Z has shape (paths, steps)."""
-    ca_f, ca_c, cb, x0, _ = consts
+    ca_f, ca_c, cb, x0, _, cm = consts
     n_paths, n_steps = Z.shape
     Xf = fp.full(x0, n_paths)
     Xc = fp.full(x0, n_paths)
     cf = fp.full(x0 - x0, n_paths) if kahan else None
     cc = fp.full(x0 - x0, n_paths) if kahan else None
+    if scheme == SCHEME_MILSTEIN:
+        one, two = fp.like(x0, 1.0), fp.like(x0, 2.0)    # exact in every format
+        fine = lambda X, z, c: milstein_update(X, z, ca_f, cb, cm, one, c)  # noqa: E731
+        coarse = lambda X, z, c: milstein_update(X, z, ca_c, cb, cm, two, c)  # noqa: E731
+    else:
+        fine = lambda X, z, c: em_update(X, z, ca_f, cb, c)  # noqa: E731
+        coarse = lambda X, z, c: em_update(X, z, ca_c, cb, c)  # noqa: E731
     for n in range(n_steps):
-        Xf, cf = em_update(Xf, Z[:, n], ca_f, cb, cf)
+        Xf, cf = fine(Xf, Z[:, n], cf)
         if level >= 1 and n % 2 == 1:
-            Xc, cc = em_update(Xc, Zc_sum(n), ca_c, cb, cc)
+            Xc, cc = coarse(Xc, Zc_sum(n), cc)
     return Xf, Xc
 
 
 def level_paths(level, paths, sde, *, rv_mode, precision, nested, kahan, seed,
-                stream=0, pset=0, diag=False, mlp_params=None):
+                stream=0, pset=0, diag=False, mlp_params=None, scheme=SCHEME_EM):
     """Per-path payoffs and terms of one MLMC level for the given path indices.
 
     Returns a dict of float64 arrays: ``Pf_hat``, ``Pc_hat`` (exact pair, when computed),
@@ -123,7 +152,7 @@ def level_paths(level, paths, sde, *, rv_mode, precision, nested, kahan, seed,
     if rv_mode == RV_EXACT or nested:
         c64 = constants(sde, level, fp.FP64)
         Z = icdf.exact(w)
-        Xf, Xc = _paths(level, Z, coarse_of(Z), c64, kahan=False)
+        Xf, Xc = _paths(level, Z, coarse_of(Z), c64, kahan=False, scheme=scheme)
         Pf = payoff(Xf, kind, c64[4])
         Pc = payoff(Xc, kind, c64[4]) if level >= 1 else np.zeros_like(Pf)
         out["Pf_hat"], out["Pc_hat"] = Pf, Pc
@@ -139,7 +168,8 @@ def level_paths(level, paths, sde, *, rv_mode, precision, nested, kahan, seed,
             Zt = _mlp.approx_icdf(w, mlp_params, precision)
         else:
             Zt = icdf.approx(w, rv_mode, precision)
-        Xf, Xc = _paths(level, Zt, coarse_of(Zt), cp, kahan=kahan and precision != fp.FP64)
+        Xf, Xc = _paths(level, Zt, coarse_of(Zt), cp, kahan=kahan and precision != fp.FP64,
+                        scheme=scheme)
         Pf = fp.to64(payoff(Xf, kind, cp[4]))
         Pc = fp.to64(payoff(Xc, kind, cp[4])) if level >= 1 else np.zeros(paths.size)
         out["Pf_bar"], out["Pc_bar"] = Pf, Pc
@@ -154,7 +184,7 @@ def level_paths(level, paths, sde, *, rv_mode, precision, nested, kahan, seed,
                 Zt64 = _mlp.approx_icdf(w, mlp_params, fp.FP64)
             else:
                 Zt64 = icdf.approx(w, rv_mode, fp.FP64)
-            Xt, _ = _paths(level, Zt64, coarse_of(Zt64), c64, kahan=False)
+            Xt, _ = _paths(level, Zt64, coarse_of(Zt64), c64, kahan=False, scheme=scheme)
             out["Xf_tilde"] = Xt
             terms[TERM_ROUNDING] = out["Xf_bar"] - Xt
     out["terms"] = terms

@@ -126,7 +126,7 @@ def test_paths_within_rounding_bound_of_exact_arithmetic(precision, kahan):
     r = mlmc.level_paths(level, paths, GBM, rv_mode=mode, precision=precision, nested=False,
                          kahan=kahan, seed=21)
     w = philox.words(21, 0, level, 0, paths, 2 ** level)
-    ca_f, ca_c, cb, x0, _ = mlmc.constants(GBM, level, precision)
+    ca_f, ca_c, cb, x0, _, _ = mlmc.constants(GBM, level, precision)
     rho = fp.UNIT_ROUNDOFF[precision]
     N = 2 ** level
     key_f, key_c = ("Pf_hat", "Pc_hat") if precision == fp.FP64 else ("Pf_bar", "Pc_bar")
@@ -181,7 +181,7 @@ def test_kahan_error_bound(dtype, rho):
 def test_lemma_2_4_rounding_error_of_state_update_has_tiny_mean():
     """eta = (X (+) R(beta)) - (X + R(beta)) over all words of a regular grid."""
     level = 6
-    ca_f, _, cb, _, _ = mlmc.constants(GBM, level, fp.FP16)
+    ca_f, _, cb, _, _, _ = mlmc.constants(GBM, level, fp.FP16)
     X = np.float16(1.2345)
     x = np.arange(2 ** 22, dtype=np.uint64) * np.uint64(1024) + np.uint64(511)
     Zt = icdf.approx(x, mlmc.RV_CUBIC, fp.FP16)
