@@ -341,6 +341,28 @@ def reports(M, E, torch):
                                "pwl16": float(((zs[M.MLMC_RV_PWL16] - zs[M.MLMC_RV_EXACT]) ** 2).mean())},
         "four_way_var": {"mlp": var(mlp_rows, 1), "pwl16": var(pwl_rows, 1)},
         "nested_path_steps_per_s": {"mlp": rate(mlp_rows), "pwl16": rate(pwl_rows)}}
+    # precision-width sweep (Figure 3's question): variance of the rounding difference
+    # X-_N - X~_N against the level for bfloat16 (8 bits), binary16 (11) and binary32 (24),
+    # without and with Kahan, piecewise cubic, payoff X_T, 2^18 paths per level
+    sweep = {}
+    gbm_x = M.gbm()
+    for name, prec in (("bf16", M.MLMC_BF16), ("fp16", M.MLMC_FP16), ("fp32", M.MLMC_FP32)):
+        for k in (0, 1):
+            v = []
+            for l in range(2, 11):
+                args = M.level_args(gbm_x, l, 2 ** 18, prec, M.MLMC_APPROX_CUBIC16, k, SEED, diag=1)
+                o = torch.zeros(8, dtype=torch.float64, device="cuda")
+                M.mlmc_level_ex(args, o)
+                torch.cuda.synchronize()
+                t = o.cpu().numpy()
+                v.append(E.level_stats(t[3], t[7], 2 ** 18)[1])
+            sweep["%s%s" % (name, "_kahan" if k else "")] = v
+    rho = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "fp32": 2.0 ** -24}
+    sweep["levels"] = list(range(2, 11))
+    sweep["bound_B_l"] = {n: [2 ** l * r * r * (1 + 0.05 * 2.0 ** -l) ** (2 * 2 ** l) * math.exp(0.04 + 0.14)
+                              for l in range(2, 11)] for n, r in rho.items()}
+    rep["rounding_variance_precision_sweep_cubic_2p18"] = sweep
+
     # adaptive MLMC with a per-level precision map from measured costs, against the plain
     # binary64 estimator at the same accuracy (call payoff, eps = 1e-5)
     from paper_2012_09739_amd import driver as D

@@ -55,6 +55,10 @@ extern "C" {
 #define MLMC_FP64 0
 #define MLMC_FP32 1
 #define MLMC_FP16 2 /* packed half2: two paths per lane */
+/* bfloat16 (8 significant bits, the binary32 exponent range), emulated: binary32 registers,
+ * every operation rounded to 8 bits, to nearest even; approximate and nested modes with
+ * the dyadic tables only (the precision-width experiments around Figure 3) */
+#define MLMC_BF16 3
 
 /* inverse-CDF kind (Section 2.1; 16 dyadic intervals of (0,1/2], mirrored) */
 #define MLMC_RV_EXACT 0   /* Z = Phi^-1(U), binary64                                   */
@@ -78,6 +82,14 @@ extern "C" {
 #define MLMC_TERM_ROUNDING 3      /* X-_N - X~_N: fine terminal state in precision p minus  */
                                   /* binary64 with the same approximate variables (Lemma  */
                                   /* 2.6), only when diag is set                          */
+
+/* time-stepping scheme of mlmc_level_args_t.scheme */
+#define MLMC_SCHEME_EM 0       /* Euler-Maruyama, X <- X (+) (A (+) B) (Section 2.2)       */
+#define MLMC_SCHEME_MILSTEIN 1 /* Milstein (named in Sections 2 and 4, not analysed there): */
+                               /* for GBM dX = (A (+) B) (+) M, M = (cm (x) X) (x)         */
+                               /* (Z (x) Z (-) k), cm = R_p(sigma^2 delta_f / 2), k = 1    */
+                               /* fine, 2 coarse (the coarse variable is the sum of two    */
+                               /* fine ones).  Exact and dyadic variables (not the MLP).   */
 
 #define MLMC_PAYOFF_X 0    /* P(X) = X_T (Section 3 takes P(X) = X)                    */
 #define MLMC_PAYOFF_CALL 1 /* P(X) = max(X_T - K, 0)                                   */
@@ -109,13 +121,13 @@ typedef struct {
 typedef struct {
     mlmc_gbm_t sde;
     int32_t level;       /* 0..24: 2^level fine steps                                 */
-    int32_t precision;   /* MLMC_FP64 / FP32 / FP16                                   */
+    int32_t precision;   /* MLMC_FP64 / FP32 / FP16 / BF16                            */
     int32_t rv_mode;     /* MLMC_EXACT, MLMC_APPROX_*, MLMC_NESTED_*                  */
     int32_t kahan;       /* 0/1: Kahan-compensated low-precision updates              */
     int32_t diag;        /* 0/1: also sample MLMC_TERM_ROUNDING                        */
     uint32_t stream;     /* Philox stream id 0..65535 (independent sample sets)       */
     uint32_t pset;       /* parameter-set id (Philox counter word 3)                  */
-    uint32_t reserved;
+    uint32_t scheme;     /* MLMC_SCHEME_EM or MLMC_SCHEME_MILSTEIN                     */
     uint64_t seed;       /* Philox key                                                */
     uint64_t n_paths;    /* samples; path_offset + n_paths <= 2^32                    */
     uint64_t path_offset;/* first path index (shards / resumes a sample set)          */
@@ -144,8 +156,10 @@ int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision
 
 /* Asynchronous level call on hip_stream.  args: host.  d_out: device, 8 doubles
  * (sum[0..3], sumsq[0..3]) written when the stream reaches the call.  d_workspace:
- * device scratch of at least mlmc_level_workspace_bytes(args) bytes, or NULL to use the
- * library's per-device scratch (calls that overlap on one device then race). */
+ * device scratch of at least mlmc_level_workspace_bytes(args) bytes (8-byte aligned; it
+ * holds the chunk partial sums and the stage rows and ticket counter of the fixed-order
+ * two-stage reduction, which the call initialises itself), or NULL to use the library's
+ * per-device scratch (calls that overlap on one device then race). */
 int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspace,
                   size_t workspace_bytes, void* hip_stream);
 

@@ -18,7 +18,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlmc.so")
 
-HIP_SOURCES = ["level_f64.hip", "level_f32.hip", "level_f16.hip", "kernels_misc.hip", "batch.hip", "mlp_train.hip", "abi.cpp"]
+HIP_SOURCES = ["level_f64.hip", "level_f32.hip", "level_f16.hip", "level_bf16.hip",
+               "level_milstein_f64.hip", "level_milstein_f32.hip", "level_milstein_f16.hip",
+               "level_milstein_bf16.hip", "kernels_misc.hip", "batch.hip", "mlp_train.hip", "abi.cpp"]
 CXX_SOURCES = ["tables.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I" + os.path.join(ROOT, "include"),

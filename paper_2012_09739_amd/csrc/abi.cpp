@@ -20,13 +20,38 @@ hipError_t launch_mlp_deploy(const float* d_params, float* image, hipStream_t s)
 hipError_t launch_level_f64(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
 hipError_t launch_level_f32(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
 hipError_t launch_level_f16(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+hipError_t launch_level_bf16(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+hipError_t launch_level_milstein_f64(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+hipError_t launch_level_milstein_f32(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+hipError_t launch_level_milstein_f16(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+hipError_t launch_level_milstein_bf16(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
 
 hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s) {
+    if (v.scheme == MLMC_SCHEME_MILSTEIN) {
+        switch (v.precision) {
+            case MLMC_FP64: return launch_level_milstein_f64(v, p, grid, block, s);
+            case MLMC_FP32: return launch_level_milstein_f32(v, p, grid, block, s);
+            case MLMC_BF16: return launch_level_milstein_bf16(v, p, grid, block, s);
+            default: return launch_level_milstein_f16(v, p, grid, block, s);
+        }
+    }
     switch (v.precision) {
         case MLMC_FP64: return launch_level_f64(v, p, grid, block, s);
         case MLMC_FP32: return launch_level_f32(v, p, grid, block, s);
+        case MLMC_BF16: return launch_level_bf16(v, p, grid, block, s);
         default: return launch_level_f16(v, p, grid, block, s);
     }
+}
+
+// R_bf16(x): a finite binary64 value rounded once to 8 significant bits, to nearest with
+// ties to even (the constants and tables of the emulated bfloat16 paths).
+double bf16_of(double x) {
+    uint64_t u;
+    std::memcpy(&u, &x, sizeof u);
+    const uint64_t d = 45;  // 53 - 8 dropped bits
+    u = (u + ((1ull << (d - 1)) - 1) + ((u >> d) & 1ull)) & ~((1ull << d) - 1);
+    std::memcpy(&x, &u, sizeof x);
+    return x;
 }
 
 namespace {
@@ -76,7 +101,7 @@ struct DevState {
     int n_cu = 256;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    void* tables[2][3] = {{nullptr}};  // [pwl, cubic][precision], 16 x (d+1) coefficients
+    void* tables[2][4] = {{nullptr}};  // [pwl, cubic][precision], 16 x (d+1) coefficients
     double* tables64[2] = {nullptr, nullptr};
     double* scratch = nullptr;
     size_t scratch_bytes = 0;
@@ -111,20 +136,24 @@ int upload_tables(DevState& st) {
         double h64[64];
         float h32[64];
         __half h16[64];
+        float hbf[64];
         for (int j = 0; j < 16; ++j)
             for (int i = 0; i <= d; ++i) {
                 const double c = src[j][i];
                 h64[j * (d + 1) + i] = c;
                 h32[j * (d + 1) + i] = (float)c;
                 h16[j * (d + 1) + i] = half_of(c);  // one rounding from binary64
+                hbf[j * (d + 1) + i] = (float)bf16_of(c);  // one rounding from binary64, exact in binary32
             }
         hipError_t e;
         if ((e = hipMalloc(&st.tables[r][MLMC_FP64], n * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMalloc(&st.tables[r][MLMC_FP32], n * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMalloc(&st.tables[r][MLMC_FP16], n * sizeof(__half))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipMalloc(&st.tables[r][MLMC_BF16], n * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMemcpy(st.tables[r][MLMC_FP64], h64, n * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(st.tables[r][MLMC_FP32], h32, n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(st.tables[r][MLMC_FP16], h16, n * sizeof(__half), hipMemcpyHostToDevice)) != hipSuccess)
+            (e = hipMemcpy(st.tables[r][MLMC_FP16], h16, n * sizeof(__half), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(st.tables[r][MLMC_BF16], hbf, n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "hipMemcpy");
         st.tables64[r] = (double*)st.tables[r][MLMC_FP64];
     }
@@ -226,8 +255,8 @@ int validate_args(const mlmc_level_args_t* a, Variant* v) {
     int rc = validate_sde(&a->sde);
     if (rc) return rc;
     if (a->level < 0 || a->level > kMaxLevel) return fail(MLMC_EINVAL, "level %d outside 0..%d", a->level, kMaxLevel);
-    if (a->precision < MLMC_FP64 || a->precision > MLMC_FP16)
-        return fail(MLMC_EINVAL, "precision %d is not MLMC_FP64/FP32/FP16", a->precision);
+    if (a->precision < MLMC_FP64 || a->precision > MLMC_BF16)
+        return fail(MLMC_EINVAL, "precision %d is not MLMC_FP64/FP32/FP16/BF16", a->precision);
     if (a->kahan != 0 && a->kahan != 1) return fail(MLMC_EINVAL, "kahan must be 0 or 1");
     if (a->diag != 0 && a->diag != 1) return fail(MLMC_EINVAL, "diag must be 0 or 1");
     if (a->stream > 0xFFFFu) return fail(MLMC_EINVAL, "stream %u exceeds 65535", a->stream);
@@ -241,6 +270,13 @@ int validate_args(const mlmc_level_args_t* a, Variant* v) {
     if (rv == MLMC_RV_EXACT && a->precision != MLMC_FP64)
         return fail(MLMC_EINVAL, "MLMC_EXACT (the plain estimator) runs in MLMC_FP64");
     if (rv == MLMC_RV_EXACT && a->diag) return fail(MLMC_EINVAL, "diag needs an approximate rv_mode");
+    if (a->precision == MLMC_BF16 && rv == MLMC_RV_MLP)
+        return fail(MLMC_EINVAL, "MLMC_BF16 runs the dyadic approximations (PWL16, CUBIC16) only");
+    if (a->scheme != MLMC_SCHEME_EM && a->scheme != MLMC_SCHEME_MILSTEIN)
+        return fail(MLMC_EINVAL, "scheme %u is not MLMC_SCHEME_EM/MILSTEIN", a->scheme);
+    if (a->scheme == MLMC_SCHEME_MILSTEIN && rv == MLMC_RV_MLP)
+        return fail(MLMC_EINVAL, "MLMC_SCHEME_MILSTEIN runs with exact and dyadic variables only");
+    v->scheme = (int)a->scheme;
     v->precision = a->precision;
     v->rv = rv;
     v->nested = nested;
@@ -292,14 +328,17 @@ int enqueue_level(DevState& st, const mlmc_level_args_t* a, const Variant& v, do
     p.out_pc_bar = out_pc_bar;
     p.out_xf_tilde = out_xf_tilde;
     hipError_t e;
-    if (n_chunks > 0) {
-        int grid, block;
-        launch_shape(st, n_chunks, &grid, &block);
-        e = launch_level(v, p, grid, block, s);
-        if (e != hipSuccess) return hip_fail(e, "level kernel launch");
-    }
+    // layout of the workspace: chunk partials, stage rows, ticket counter
+    double* stage = partials + (n_chunks == 0 ? 1 : n_chunks) * kPartial;
+    uint32_t* counter = (uint32_t*)(stage + kStageRowsMax * kPartial);
+    p.reduce_counter = d_out ? counter : nullptr;
+    // launched also for no chunks: the level kernel arms the reduction's counter
+    int grid, block;
+    launch_shape(st, n_chunks, &grid, &block);
+    e = launch_level(v, p, grid, block, s);
+    if (e != hipSuccess) return hip_fail(e, "level kernel launch");
     if (d_out) {
-        e = launch_reduce(partials, n_chunks, d_out, s);
+        e = launch_reduce(partials, n_chunks, stage, counter, d_out, s);
         if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
     }
     return MLMC_OK;
@@ -329,17 +368,21 @@ int validate_sde_public(const mlmc_gbm_t* s) { return validate_sde(s); }
 // binary64 constants of one level, then one rounding to each working precision
 void fill_level_params(LevelParams* p, const mlmc_gbm_t& s, int level, int precision, uint64_t n_paths,
                        uint64_t path_offset, uint64_t seed, uint32_t stream, uint32_t pset) {
-    (void)precision;
     std::memset(p, 0, sizeof *p);
     const double dt = s.T * std::ldexp(1.0, -level);
     const double ca = s.mu * dt;
     const double cac = s.mu * (2.0 * dt);
     const double cb = s.sigma * std::sqrt(dt);
-    p->ca_f64 = ca; p->cac_f64 = cac; p->cb_f64 = cb; p->x0_f64 = s.x0; p->k_f64 = s.strike;
+    const double cm = 0.5 * s.sigma * s.sigma * dt;
+    p->ca_f64 = ca; p->cac_f64 = cac; p->cb_f64 = cb; p->x0_f64 = s.x0; p->k_f64 = s.strike; p->cm_f64 = cm;
     p->ca_f32 = (float)ca; p->cac_f32 = (float)cac; p->cb_f32 = (float)cb; p->x0_f32 = (float)s.x0;
-    p->k_f32 = (float)s.strike;
+    p->k_f32 = (float)s.strike; p->cm_f32 = (float)cm;
+    if (precision == MLMC_BF16) {  // one rounding from binary64 to 8 bits, exact in binary32
+        p->ca_f32 = (float)bf16_of(ca); p->cac_f32 = (float)bf16_of(cac); p->cb_f32 = (float)bf16_of(cb);
+        p->x0_f32 = (float)bf16_of(s.x0); p->k_f32 = (float)bf16_of(s.strike); p->cm_f32 = (float)bf16_of(cm);
+    }
     p->ca_f16 = half_of(ca); p->cac_f16 = half_of(cac); p->cb_f16 = half_of(cb);
-    p->x0_f16 = half_of(s.x0); p->k_f16 = half_of(s.strike);
+    p->x0_f16 = half_of(s.x0); p->k_f16 = half_of(s.strike); p->cm_f16 = half_of(cm);
     p->payoff = s.payoff;
     p->level = level;
     p->n_steps = 1u << level;
@@ -357,7 +400,7 @@ int device_info(DeviceInfo* out) {
     if (rc) return rc;
     out->n_cu = st->n_cu;
     for (int r = 0; r < 2; ++r) {
-        for (int q = 0; q < 3; ++q) out->tables[r][q] = st->tables[r][q];
+        for (int q = 0; q < 4; ++q) out->tables[r][q] = st->tables[r][q];
         out->tables64[r] = st->tables64[r];
     }
     out->mlp = st->mlp;
@@ -415,8 +458,7 @@ const char* mlmc_last_error(void) { return g_error.c_str(); }
 size_t mlmc_level_workspace_bytes(const mlmc_level_args_t* args) {
     Variant v;
     if (validate_args(args, &v)) return 0;
-    const uint64_t n = n_chunks_of(args);
-    return (size_t)(n == 0 ? 1 : n) * kPartial * sizeof(double);
+    return level_workspace_bytes(n_chunks_of(args));
 }
 
 int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspace, size_t workspace_bytes,
@@ -425,7 +467,7 @@ int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspac
     int rc = validate_args(args, &v);
     if (rc) return rc;
     if (!d_out) return fail(MLMC_EINVAL, "d_out is NULL");
-    const size_t need = (size_t)(n_chunks_of(args) == 0 ? 1 : n_chunks_of(args)) * kPartial * sizeof(double);
+    const size_t need = level_workspace_bytes(n_chunks_of(args));
     if (d_workspace && workspace_bytes < need)
         return fail(MLMC_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
     DevState* st;
@@ -461,7 +503,7 @@ int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision
     if (rc) return rc;
     DevState* st;
     if ((rc = device_state(&st))) return rc;
-    const size_t need = (size_t)(n_chunks_of(&a) == 0 ? 1 : n_chunks_of(&a)) * kPartial * sizeof(double);
+    const size_t need = level_workspace_bytes(n_chunks_of(&a));
     if ((rc = ensure_scratch(*st, need))) return rc;
     hipError_t e = hipEventRecord(st->ev0, st->stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -493,7 +535,7 @@ int mlmc_paths(const mlmc_level_args_t* args, double* d_pf_hat, double* d_pc_hat
     if (rc) return rc;
     DevState* st;
     if ((rc = device_state(&st))) return rc;
-    const size_t need = (size_t)(n_chunks_of(args) == 0 ? 1 : n_chunks_of(args)) * kPartial * sizeof(double);
+    const size_t need = level_workspace_bytes(n_chunks_of(args));
     if ((rc = ensure_scratch(*st, need))) return rc;
     return enqueue_level(*st, args, v, nullptr, st->scratch, d_pf_hat, d_pc_hat, d_pf_bar, d_pc_bar, d_xf_tilde,
                          (hipStream_t)hip_stream);
@@ -518,7 +560,9 @@ int mlmc_uniforms(uint64_t seed, uint32_t stream, int level, uint32_t pset, uint
 int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double* d_out, void* hip_stream) {
     if ((!d_words || !d_out) && n > 0) return fail(MLMC_EINVAL, "NULL buffer");
     if (rv < MLMC_RV_EXACT || rv > MLMC_RV_MLP) return fail(MLMC_EINVAL, "rv %d is not an MLMC_RV_* kind", rv);
-    if (precision < MLMC_FP64 || precision > MLMC_FP16) return fail(MLMC_EINVAL, "precision %d invalid", precision);
+    if (precision < MLMC_FP64 || precision > MLMC_BF16) return fail(MLMC_EINVAL, "precision %d invalid", precision);
+    if (precision == MLMC_BF16 && rv != MLMC_RV_PWL16 && rv != MLMC_RV_CUBIC16)
+        return fail(MLMC_EINVAL, "MLMC_BF16 is available for the dyadic approximations only");
     DevState* st;
     int rc = device_state(&st);
     if (rc) return rc;
@@ -547,7 +591,7 @@ int mlmc_mlp_load(const float* d_params, void* hip_stream) {
 int mlmc_table(int rv, int precision, double* h_out) {
     if (!h_out) return fail(MLMC_EINVAL, "h_out is NULL");
     if (rv != MLMC_RV_PWL16 && rv != MLMC_RV_CUBIC16) return fail(MLMC_EINVAL, "rv must be PWL16 or CUBIC16");
-    if (precision < MLMC_FP64 || precision > MLMC_FP16) return fail(MLMC_EINVAL, "precision %d invalid", precision);
+    if (precision < MLMC_FP64 || precision > MLMC_BF16) return fail(MLMC_EINVAL, "precision %d invalid", precision);
     const HostTables& ht = host_tables();
     if (!ht.ok) return fail(MLMC_EHIP, "dyadic table construction failed");
     const double(*src)[4] = rv == MLMC_RV_PWL16 ? ht.pwl : ht.cubic;
@@ -558,6 +602,7 @@ int mlmc_table(int rv, int precision, double* h_out) {
             double r = c;
             if (precision == MLMC_FP32) r = (double)(float)c;
             if (precision == MLMC_FP16) r = (double)__half2float(half_of(c));
+            if (precision == MLMC_BF16) r = bf16_of(c);
             h_out[j * 4 + i] = r;
         }
     return MLMC_OK;

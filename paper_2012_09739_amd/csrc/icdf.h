@@ -192,6 +192,29 @@ __device__ __forceinline__ float prescaled_coeff(float c, int i) {
     return __builtin_ldexpf(c, -31 * i);
 }
 
+// R_bf16(x): x rounded to 8 significant bits, to nearest with ties to even, from the bit
+// pattern (finite x); the result is a binary32 value.  Rounding the correctly rounded
+// binary32 result of + - x on 8-bit operands gives the correctly rounded bfloat16 result
+// (24 >= 2 * 8 + 2).
+__device__ __forceinline__ float round_bf16(float x) {
+    const uint32_t u = __float_as_uint(x);
+    const uint32_t r = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    return __uint_as_float(r);
+}
+
+// Z~ in emulated bfloat16; tab holds 16 rows of (DEG + 1) coefficients rounded to bfloat16
+// (as binary32 values).  The coordinate is formed in binary32 and narrowed, R_bf16(R_32(t)).
+template <int DEG>
+__device__ __forceinline__ float icdf_dyadic_bf16(uint32_t word, const float* __restrict__ tab) {
+    const DyadicPos p = dyadic_locate(word);
+    const float t = round_bf16((float)p.T * 0x1p-31f);
+    const float* c = tab + p.row * (DEG + 1);
+    float q = c[DEG];
+#pragma unroll
+    for (int i = DEG - 1; i >= 0; --i) q = round_bf16(round_bf16(q * t) + c[i]);
+    return apply_sign(q, p.sign);
+}
+
 // Z~ in binary64 (the high-precision approximate variable of the diagnostic paths).
 template <int DEG>
 __device__ __forceinline__ double icdf_dyadic_f64(uint32_t word, const double* __restrict__ tab) {

@@ -19,12 +19,12 @@ constexpr int kTableRows = 16;
 // Per-launch parameters of one MLMC level (one parameter set).  Constants are rounded
 // on the host from binary64, once, to the working precision p (R_p(mu delta) etc.).
 struct LevelParams {
-    // exact pair (binary64)
-    double ca_f64, cac_f64, cb_f64, x0_f64, k_f64;
-    // approximate pair in binary32 (also used for the binary64 approximate pair via *_f64)
-    float ca_f32, cac_f32, cb_f32, x0_f32, k_f32;
+    // exact pair (binary64); cm is the Milstein constant sigma^2 delta_f / 2
+    double ca_f64, cac_f64, cb_f64, x0_f64, k_f64, cm_f64;
+    // approximate pair in binary32, or in emulated bfloat16 (then rounded to 8 bits)
+    float ca_f32, cac_f32, cb_f32, x0_f32, k_f32, cm_f32;
     // approximate pair in binary16
-    __half ca_f16, cac_f16, cb_f16, x0_f16, k_f16;
+    __half ca_f16, cac_f16, cb_f16, x0_f16, k_f16, cm_f16;
     int payoff;
     int level;
     uint32_t n_steps;
@@ -38,6 +38,7 @@ struct LevelParams {
     const void* mlp;       // MLP inference image (rv = MLP)
     const void* exact_tab; // ExactTable: log cells and piecewise coefficients (exact inverse CDF)
     double* partials;      // [n_chunks][kPartial] chunk partial sums
+    uint32_t* reduce_counter;  // ticket counter of the two-stage reduction (zeroed here), or null
     // optional per-path outputs (device, n_paths entries each, may be null)
     double* out_pf_hat;
     double* out_pc_hat;
@@ -48,16 +49,25 @@ struct LevelParams {
 
 // Template variant selector.
 struct Variant {
-    int precision;  // MLMC_FP64 / MLMC_FP32 / MLMC_FP16
+    int precision;  // MLMC_FP64 / MLMC_FP32 / MLMC_FP16 / MLMC_BF16
     int rv;         // MLMC_RV_EXACT / PWL16 / CUBIC16 / MLP
     bool nested;
     bool kahan;
     bool diag;
+    int scheme;     // MLMC_SCHEME_EM / MLMC_SCHEME_MILSTEIN
 };
 
 // Launch helpers implemented in the .hip translation units.
 hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
-hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* d_out, hipStream_t s);
+hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* stage, uint32_t* counter,
+                         double* d_out, hipStream_t s);
+
+// Workspace of one level call: the chunk partials, the stage rows of the two-stage
+// reduction (at most 128 rows of kPartial doubles) and its ticket counter.
+constexpr uint64_t kStageRowsMax = 128;
+inline size_t level_workspace_bytes(uint64_t n_chunks) {
+    return (size_t)((n_chunks == 0 ? 1 : n_chunks) + kStageRowsMax) * kPartial * sizeof(double) + 64;
+}
 hipError_t launch_uniforms(uint64_t seed, uint32_t ctr2, uint32_t pset, uint64_t path0,
                            uint64_t n_paths, uint32_t n_steps, uint32_t* d_words, hipStream_t s);
 hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, const void* table,
@@ -66,7 +76,7 @@ hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precisio
 // Device resources the library keeps for the current device (lazily initialised).
 struct DeviceInfo {
     int n_cu;
-    const void* tables[2][3];  // [pwl, cubic][precision]
+    const void* tables[2][4];  // [pwl, cubic][precision]
     const double* tables64[2];
     const void* mlp;
     bool mlp_loaded;

@@ -15,10 +15,11 @@ namespace {
 // t, t + 256, ... sequentially, then a fixed tree over the 256 threads.  The order depends
 // only on n_chunks, so results do not depend on the level kernel's launch shape, and the
 // batched sweep (one block per item) reproduces the single-level sums bit for bit.
-__global__ __launch_bounds__(kReduceBlock) __attribute__((amdgpu_waves_per_eu(1, 1))) void reduce_chunks(const double* __restrict__ partials,
-                                                              uint64_t n_chunks, double* __restrict__ out) {
+__global__ __launch_bounds__(kReduceBlock) void reduce_chunks(const double* __restrict__ partials, uint64_t n_chunks,
+                                                              double* stage, uint32_t* counter,
+                                                              double* __restrict__ out) {
     __shared__ double s[kPartial][kReduceBlock];
-    reduce_rows_block(partials, n_chunks, out, s);
+    reduce_two_stage(partials, n_chunks, stage, counter, out, blockIdx.x, s);
 }
 
 __global__ void uniforms_kernel(uint32_t k0, uint32_t k1, uint32_t ctr2, uint32_t pset, uint64_t path0,
@@ -56,6 +57,8 @@ __global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, cons
             z = icdf_dyadic_f64<DEG>(w, (const double*)table);
         } else if constexpr (PREC == MLMC_FP32) {
             z = (double)icdf_dyadic_f32<DEG>(w, (const float*)table);
+        } else if constexpr (PREC == MLMC_BF16) {
+            z = (double)icdf_dyadic_bf16<DEG>(w, (const float*)table);
         } else {
             z = (double)__half2float(icdf_dyadic_f16<DEG>(w, (const __half*)table));
         }
@@ -70,8 +73,10 @@ int grid_for(uint64_t n, int block) {
 
 }  // namespace
 
-hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* d_out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_chunks, dim3(1), dim3(kReduceBlock), 0, s, partials, n_chunks, d_out);
+hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* stage, uint32_t* counter,
+                         double* d_out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_chunks, dim3(stage_blocks(n_chunks)), dim3(kReduceBlock), 0, s, partials, n_chunks,
+                       stage, counter, d_out);
     return hipGetLastError();
 }
 
@@ -99,9 +104,11 @@ hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precisio
     MLMC_ICDF_CASE(MLMC_RV_PWL16, MLMC_FP64)
     MLMC_ICDF_CASE(MLMC_RV_PWL16, MLMC_FP32)
     MLMC_ICDF_CASE(MLMC_RV_PWL16, MLMC_FP16)
+    MLMC_ICDF_CASE(MLMC_RV_PWL16, MLMC_BF16)
     MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_FP64)
     MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_FP32)
     MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_FP16)
+    MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_BF16)
     MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP64)
     MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP32)
     MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP16)

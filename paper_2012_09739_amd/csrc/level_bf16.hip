@@ -1,0 +1,10 @@
+// Level kernel instances for precision MLMC_BF16, Euler-Maruyama.
+#include "level_launch.h"
+
+namespace mlmc {
+
+hipError_t launch_level_bf16(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s) {
+    return launch_level_for<MLMC_BF16, MLMC_SCHEME_EM, false>(v, p, grid, block, s);
+}
+
+}  // namespace mlmc

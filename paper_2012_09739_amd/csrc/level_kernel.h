@@ -11,6 +11,10 @@
 // Arithmetic (Section 2.2): X <- X (+) (A (+) B), A = ca (x) X, B = (cb (x) X) (x) Z with
 // one rounding per operation (the build uses -ffp-contract=off), and the optional
 // Kahan-compensated update of Algorithm 1 / Code 1 on every low-precision path.
+// The Milstein instances (the higher-order scheme of Sections 2 and 4) add, for GBM, the
+// rounded correction M = (cm (x) X) (x) (Z (x) Z (-) k), cm = R_p(sigma^2 delta_f / 2),
+// as dX = (A (+) B) (+) M, with k = 1 on the fine path and k = 2 on the coarse path (whose
+// variable is the sum of two fine ones).
 #pragma once
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -26,46 +30,76 @@
 namespace mlmc {
 
 // ---- one Euler-Maruyama update in precision T --------------------------------------
-template <typename T>
-__device__ __forceinline__ void em_step(T& X, T z, T ca, T cb) {
-    const T A = ca * X;
-    const T B = (cb * X) * z;
-    const T dX = A + B;
-    X = X + dX;
+// R is the rounding applied to the result of every operation: none for the IEEE formats
+// (the hardware rounds), R_bf16 for emulated bfloat16.
+struct NoRound {
+    template <typename T>
+    __device__ __forceinline__ T operator()(T x) const { return x; }
+};
+struct RoundBF16 {
+    __device__ __forceinline__ float operator()(float x) const { return round_bf16(x); }
+};
+
+// The increment dX of one step: A (+) B, and for Milstein (A (+) B) (+) M.
+template <int SCHEME, typename T, typename R>
+__device__ __forceinline__ T increment(T X, T z, T ca, T cb, T cm, T k, R r) {
+    const T A = r(ca * X);
+    const T B = r(r(cb * X) * z);
+    const T dX = r(A + B);
+    if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) {
+        const T M = r(r(cm * X) * r(r(z * z) - k));
+        return r(dX + M);
+    } else {
+        return dX;
+    }
 }
 
-template <typename T>
-__device__ __forceinline__ void em_step_kahan(T& X, T& c, T z, T ca, T cb) {
-    const T A = ca * X;
-    const T B = (cb * X) * z;
-    const T dX = A + B;
-    const T y = dX - c;
-    const T s = X + y;
-    c = (s - X) - y;
+template <int SCHEME, typename T, typename R = NoRound>
+__device__ __forceinline__ void em_step(T& X, T z, T ca, T cb, T cm, T k, R r = R{}) {
+    X = r(X + increment<SCHEME>(X, z, ca, cb, cm, k, r));
+}
+
+template <int SCHEME, typename T, typename R = NoRound>
+__device__ __forceinline__ void em_step_kahan(T& X, T& c, T z, T ca, T cb, T cm, T k, R r = R{}) {
+    const T dX = increment<SCHEME>(X, z, ca, cb, cm, k, r);
+    const T y = r(dX - c);
+    const T s = r(X + y);
+    c = r(r(s - X) - y);
     X = s;
 }
 
-__device__ __forceinline__ void em_step_h2(__half2& X, __half2 z, __half2 ca, __half2 cb) {
+template <int SCHEME>
+__device__ __forceinline__ __half2 increment_h2(__half2 X, __half2 z, __half2 ca, __half2 cb, __half2 cm, __half2 k) {
     const __half2 A = __hmul2(ca, X);
     const __half2 B = __hmul2(__hmul2(cb, X), z);
     const __half2 dX = __hadd2(A, B);
-    X = __hadd2(X, dX);
+    if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) {
+        const __half2 M = __hmul2(__hmul2(cm, X), __hsub2(__hmul2(z, z), k));
+        return __hadd2(dX, M);
+    } else {
+        return dX;
+    }
 }
 
-__device__ __forceinline__ void em_step_kahan_h2(__half2& X, __half2& c, __half2 z, __half2 ca, __half2 cb) {
-    const __half2 A = __hmul2(ca, X);
-    const __half2 B = __hmul2(__hmul2(cb, X), z);
-    const __half2 dX = __hadd2(A, B);
+template <int SCHEME>
+__device__ __forceinline__ void em_step_h2(__half2& X, __half2 z, __half2 ca, __half2 cb, __half2 cm, __half2 k) {
+    X = __hadd2(X, increment_h2<SCHEME>(X, z, ca, cb, cm, k));
+}
+
+template <int SCHEME>
+__device__ __forceinline__ void em_step_kahan_h2(__half2& X, __half2& c, __half2 z, __half2 ca, __half2 cb, __half2 cm,
+                                                 __half2 k) {
+    const __half2 dX = increment_h2<SCHEME>(X, z, ca, cb, cm, k);
     const __half2 y = __hsub2(dX, c);
     const __half2 s = __hadd2(X, y);
     c = __hsub2(__hsub2(s, X), y);
     X = s;
 }
 
-template <typename T>
-__device__ __forceinline__ T payoff(T X, T K, int kind) {
+template <typename T, typename R = NoRound>
+__device__ __forceinline__ T payoff(T X, T K, int kind, R r = R{}) {
     if (kind == MLMC_PAYOFF_X) return X;
-    const T d = X - K;
+    const T d = r(X - K);
     return d > T(0) ? d : T(0);
 }
 
@@ -91,10 +125,12 @@ __device__ __forceinline__ void stage_exact_table(unsigned char* dst, const void
 
 // ---- the kernel ------------------------------------------------------------------------
 // Approximate variable of one word in the working precision (binary64 or binary32).
-template <int RV, int DEG, typename T>
+template <int RV, int DEG, typename T, int PREC = MLMC_FP32>
 __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* mlpw, const LogCell* logtab) {
     if constexpr (RV == MLMC_RV_MLP) {
         return (T)icdf_mlp_f32(w, mlpw, logtab);
+    } else if constexpr (PREC == MLMC_BF16) {
+        return icdf_dyadic_bf16<DEG>(w, (const float*)tab);
     } else if constexpr (sizeof(T) == 8) {
         return icdf_dyadic_f64<DEG>(w, (const double*)tab);
     } else {
@@ -106,7 +142,7 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
 // level and writes the chunk's 8 partial sums to prm.partials[chunk].  s_tab is the
 // coefficient table in the working precision (binary32: prescaled, see prescaled_coeff) and
 // s_tab64 the binary64 one (diagnostic), both in LDS.
-template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false>
+template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
 __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
                                           const double* s_tab64, const ExactTable* s_ex) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
@@ -116,6 +152,8 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
     constexpr bool kKahan = KAHAN && PREC != MLMC_FP64;
     constexpr int L = (PREC == MLMC_FP16) ? 2 : 1;  // paths per lane
     using AT = typename std::conditional<PREC == MLMC_FP64, double, float>::type;
+    using Rnd = typename std::conditional<PREC == MLMC_BF16, RoundBF16, NoRound>::type;
+    const Rnd rnd{};
     const AT* s_tab = (const AT*)s_tab_v;
     const __half* s_tab16 = (const __half*)s_tab_v;
     const float* mlpw = (const float*)s_tab_v;  // the MLP image when RV is MLMC_RV_MLP
@@ -145,10 +183,13 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
     const AT ca_b = (AT)(PREC == MLMC_FP64 ? prm.ca_f64 : prm.ca_f32);
     const AT cac_b = (AT)(PREC == MLMC_FP64 ? prm.cac_f64 : prm.cac_f32);
     const AT cb_b = (AT)(PREC == MLMC_FP64 ? prm.cb_f64 : prm.cb_f32);
+    const AT cm_b = (AT)(PREC == MLMC_FP64 ? prm.cm_f64 : prm.cm_f32);
+    const AT one_b = (AT)1, two_b = (AT)2;  // the Milstein offsets k, exact in every format
     __half2 Xf2 = __half2half2(prm.x0_f16), Xc2 = Xf2, cf2 = __float2half2_rn(0.0f), cc2 = cf2,
             z2_prev = cf2;
     const __half2 ca2 = __half2half2(prm.ca_f16), cac2 = __half2half2(prm.cac_f16),
-                  cb2 = __half2half2(prm.cb_f16);
+                  cb2 = __half2half2(prm.cb_f16), cm2 = __half2half2(prm.cm_f16);
+    const __half2 one2 = __float2half2_rn(1.0f), two2 = __float2half2_rn(2.0f);
 
     ExactConsts kc{};
     if constexpr (kNeedExact) kc = exact_consts();
@@ -178,19 +219,20 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     const double z = zx[l][i];
-                    em_step<double>(Xfh[l], z, prm.ca_f64, prm.cb_f64);
-                    if (coarse) em_step<double>(Xch[l], zh_prev[l] + z, prm.cac_f64, prm.cb_f64);
+                    em_step<SCHEME, double>(Xfh[l], z, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
+                    if (coarse)
+                        em_step<SCHEME, double>(Xch[l], zh_prev[l] + z, prm.cac_f64, prm.cb_f64, prm.cm_f64, 2.0);
                     else zh_prev[l] = z;
                 }
             }
             if constexpr (kNeedApprox && PREC != MLMC_FP16) {
-                const AT z = approx_rv<RV, DEG, AT>(r[0].w[i], s_tab, mlpw, s_ex->log);
+                const AT z = approx_rv<RV, DEG, AT, PREC>(r[0].w[i], s_tab, mlpw, s_ex->log);
                 if constexpr (kKahan) {
-                    em_step_kahan<AT>(Xfb, cfb, z, ca_b, cb_b);
-                    if (coarse) em_step_kahan<AT>(Xcb, ccb, zb_prev + z, cac_b, cb_b);
+                    em_step_kahan<SCHEME, AT>(Xfb, cfb, z, ca_b, cb_b, cm_b, one_b, rnd);
+                    if (coarse) em_step_kahan<SCHEME, AT>(Xcb, ccb, rnd(zb_prev + z), cac_b, cb_b, cm_b, two_b, rnd);
                 } else {
-                    em_step<AT>(Xfb, z, ca_b, cb_b);
-                    if (coarse) em_step<AT>(Xcb, zb_prev + z, cac_b, cb_b);
+                    em_step<SCHEME, AT>(Xfb, z, ca_b, cb_b, cm_b, one_b, rnd);
+                    if (coarse) em_step<SCHEME, AT>(Xcb, rnd(zb_prev + z), cac_b, cb_b, cm_b, two_b, rnd);
                 }
                 if (!coarse) zb_prev = z;
             }
@@ -205,11 +247,11 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
                 }
                 const __half2 z = __halves2half2(z0, z1);
                 if constexpr (kKahan) {
-                    em_step_kahan_h2(Xf2, cf2, z, ca2, cb2);
-                    if (coarse) em_step_kahan_h2(Xc2, cc2, __hadd2(z2_prev, z), cac2, cb2);
+                    em_step_kahan_h2<SCHEME>(Xf2, cf2, z, ca2, cb2, cm2, one2);
+                    if (coarse) em_step_kahan_h2<SCHEME>(Xc2, cc2, __hadd2(z2_prev, z), cac2, cb2, cm2, two2);
                 } else {
-                    em_step_h2(Xf2, z, ca2, cb2);
-                    if (coarse) em_step_h2(Xc2, __hadd2(z2_prev, z), cac2, cb2);
+                    em_step_h2<SCHEME>(Xf2, z, ca2, cb2, cm2, one2);
+                    if (coarse) em_step_h2<SCHEME>(Xc2, __hadd2(z2_prev, z), cac2, cb2, cm2, two2);
                 }
                 if (!coarse) z2_prev = z;
             }
@@ -219,7 +261,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
                     double zt;
                     if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw, s_ex->log);
                     else zt = icdf_dyadic_f64<DEG>(r[l].w[i], s_tab64);
-                    em_step<double>(Xft[l], zt, prm.ca_f64, prm.cb_f64);
+                    em_step<SCHEME, double>(Xft[l], zt, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
                 }
             }
         }
@@ -247,8 +289,8 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
                 xfb = (double)__half2float(xf);
             } else {
                 const AT kk = (AT)(PREC == MLMC_FP64 ? prm.k_f64 : prm.k_f32);
-                pfb = (double)payoff<AT>(Xfb, kk, prm.payoff);
-                pcb = has_coarse ? (double)payoff<AT>(Xcb, kk, prm.payoff) : 0.0;
+                pfb = (double)payoff<AT>(Xfb, kk, prm.payoff, rnd);
+                pcb = has_coarse ? (double)payoff<AT>(Xcb, kk, prm.payoff, rnd) : 0.0;
                 xfb = (double)Xfb;
             }
         }
@@ -294,8 +336,9 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
 }
 
 // SHORT: the instance for levels with fewer than 4 fine steps (exact variables one word at a time).
-template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC != MLMC_FP16 && RV != MLMC_RV_MLP ? 7 : 1))) void level_kernel(const LevelParams prm) {
+// SCHEME: MLMC_SCHEME_EM or MLMC_SCHEME_MILSTEIN.
+template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == MLMC_FP32 || PREC == MLMC_FP64) && RV != MLMC_RV_MLP ? 7 : 1))) void level_kernel(const LevelParams prm) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
     constexpr int L = (PREC == MLMC_FP16) ? 2 : 1;
@@ -307,6 +350,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC != MLM
     __shared__ double s_tab64[kTableRows * 4];
     __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
     constexpr bool kNeedLog = RV == MLMC_RV_EXACT || NESTED || RV == MLMC_RV_MLP;
+    // arm the ticket counter of the reduction that follows this kernel on the stream
+    if (prm.reduce_counter && blockIdx.x == 0 && threadIdx.x == 0) *prm.reduce_counter = 0u;
     __shared__ __align__(16) unsigned char s_ex_raw[kNeedLog ? sizeof(ExactTable) : 16];
     const ExactTable* s_ex = (const ExactTable*)s_ex_raw;
     if constexpr (kNeedLog) {
@@ -317,6 +362,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC != MLM
         for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
             if constexpr (PREC == MLMC_FP16) s_tab16[i] = ((const __half*)prm.table)[i];
             else if constexpr (PREC == MLMC_FP32) s_tab[i] = prescaled_coeff(((const float*)prm.table)[i], i % (DEG + 1));
+            else if constexpr (PREC == MLMC_BF16) s_tab[i] = ((const float*)prm.table)[i];  // bfloat16 values, unscaled
             else s_tab[i] = ((const AT*)prm.table)[i];
             if constexpr (DIAG) s_tab64[i] = prm.table64[i];
         }
@@ -334,7 +380,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC != MLM
     constexpr uint32_t kChunk = kWave * L;
     const uint64_t n_chunks = (prm.n_paths + kChunk - 1) / kChunk;
     for (uint64_t chunk = wave; chunk < n_chunks; chunk += n_waves)
-        run_chunk<PREC, RV, NESTED, KAHAN, DIAG, SHORT>(prm, chunk, lane, tab, s_tab64, s_ex);
+        run_chunk<PREC, RV, NESTED, KAHAN, DIAG, SHORT, SCHEME>(prm, chunk, lane, tab, s_tab64, s_ex);
 }
 
 }  // namespace mlmc

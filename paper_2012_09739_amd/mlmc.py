@@ -15,11 +15,13 @@ LIB_PATH = os.path.join(HERE, "libmlmc.so")
 
 MLMC_OK, MLMC_EINVAL, MLMC_ENOMEM, MLMC_ENODEV, MLMC_EHIP, MLMC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MLMC_FP64, MLMC_FP32, MLMC_FP16 = 0, 1, 2
+MLMC_BF16 = 3   # emulated bfloat16 (dyadic approximations only)
 MLMC_RV_EXACT, MLMC_RV_PWL16, MLMC_RV_CUBIC16, MLMC_RV_MLP = 0, 1, 2, 3
 MLMC_EXACT, MLMC_APPROX_PWL16, MLMC_APPROX_CUBIC16, MLMC_APPROX_MLP = 0, 1, 2, 3
 MLMC_NESTED_PWL16, MLMC_NESTED_CUBIC16, MLMC_NESTED_MLP = 5, 6, 7
 MLMC_TERM_TWO_WAY, MLMC_TERM_FOUR_WAY, MLMC_TERM_TWO_WAY_EXACT, MLMC_TERM_ROUNDING = 0, 1, 2, 3
 MLMC_PAYOFF_X, MLMC_PAYOFF_CALL = 0, 1
+MLMC_SCHEME_EM, MLMC_SCHEME_MILSTEIN = 0, 1
 
 ERROR_NAMES = {MLMC_EINVAL: "MLMC_EINVAL", MLMC_ENOMEM: "MLMC_ENOMEM", MLMC_ENODEV: "MLMC_ENODEV",
                MLMC_EHIP: "MLMC_EHIP", MLMC_EUNSUPPORTED: "MLMC_EUNSUPPORTED"}
@@ -45,7 +47,7 @@ class mlmc_result_t(ctypes.Structure):
 class mlmc_level_args_t(ctypes.Structure):
     _fields_ = [("sde", mlmc_gbm_t), ("level", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rv_mode", ctypes.c_int32), ("kahan", ctypes.c_int32), ("diag", ctypes.c_int32),
-                ("stream", ctypes.c_uint32), ("pset", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("stream", ctypes.c_uint32), ("pset", ctypes.c_uint32), ("scheme", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("n_paths", ctypes.c_uint64), ("path_offset", ctypes.c_uint64)]
 
 
@@ -145,11 +147,11 @@ def gbm(mu=0.05, sigma=0.2, x0=1.0, T=1.0, payoff=MLMC_PAYOFF_X, strike=1.0):
 
 
 def level_args(sde, level, n_paths, precision, rv_mode, kahan=0, seed=0, *, diag=0, stream=None, pset=0,
-               path_offset=0):
+               path_offset=0, scheme=MLMC_SCHEME_EM):
     """mlmc_level_args_t; stream defaults to 1 for nested modes and 0 otherwise."""
     if stream is None:
         stream = 1 if rv_mode >= MLMC_NESTED_PWL16 else 0
-    return mlmc_level_args_t(sde, level, precision, rv_mode, int(kahan), int(diag), stream, pset, 0, seed,
+    return mlmc_level_args_t(sde, level, precision, rv_mode, int(kahan), int(diag), stream, pset, scheme, seed,
                              n_paths, path_offset)
 
 

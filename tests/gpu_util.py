@@ -23,11 +23,11 @@ def rv_mode_code(rv, nested):
 
 
 def gpu_paths(sde, level, n_paths, precision, rv, nested, kahan, seed, *, diag=False, stream=None,
-              path_offset=0, pset=0):
+              path_offset=0, pset=0, scheme=0):
     """Per-path payoffs from mlmc_paths (same kernel and launch as the level sums)."""
     torch = torch_cuda()
     args = M.level_args(gbm_struct(sde), level, n_paths, precision, rv_mode_code(rv, nested), kahan, seed,
-                        diag=int(diag), stream=stream, pset=pset, path_offset=path_offset)
+                        diag=int(diag), stream=stream, pset=pset, path_offset=path_offset, scheme=scheme)
     bufs = {k: torch.full((max(n_paths, 1),), float("nan"), dtype=torch.float64, device="cuda")
             for k in ("pf_hat", "pc_hat", "pf_bar", "pc_bar", "xf_tilde")}
     M.mlmc_paths(args, **bufs)

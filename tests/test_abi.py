@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import paper_2012_09739_amd as M
-from oracle import tables
+from oracle import fp, tables
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mlmc.h")
 
@@ -42,7 +42,8 @@ def _gpu_visible():
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(level=-1), M.MLMC_EINVAL), (dict(level=25), M.MLMC_EINVAL), (dict(precision=3), M.MLMC_EINVAL),
+    (dict(level=-1), M.MLMC_EINVAL), (dict(level=25), M.MLMC_EINVAL), (dict(precision=4), M.MLMC_EINVAL),
+    (dict(precision=M.MLMC_BF16), M.MLMC_EINVAL), (dict(precision=M.MLMC_BF16, rv_mode=M.MLMC_NESTED_MLP), M.MLMC_EINVAL),
     (dict(rv_mode=4), M.MLMC_EINVAL), (dict(rv_mode=8), M.MLMC_EINVAL), (dict(kahan=2), M.MLMC_EINVAL),
     (dict(precision=M.MLMC_FP32, rv_mode=M.MLMC_EXACT), M.MLMC_EINVAL), (dict(n_paths=2 ** 32 + 1), M.MLMC_EINVAL)])
 def test_invalid_arguments(kw, code):
@@ -52,6 +53,16 @@ def test_invalid_arguments(kw, code):
         M.mlmc_level(M.gbm(), a["level"], a["n_paths"], a["precision"], a["rv_mode"], a["kahan"], 0)
     assert e.value.code == code
     assert M.mlmc_last_error()
+
+
+@pytest.mark.parametrize("rv_mode,scheme", [(M.MLMC_NESTED_MLP, M.MLMC_SCHEME_MILSTEIN), (M.MLMC_APPROX_MLP, 1),
+                                            (M.MLMC_NESTED_PWL16, 2), (M.MLMC_EXACT, 7)])
+def test_invalid_scheme(rv_mode, scheme):
+    precision = M.MLMC_FP64 if rv_mode == M.MLMC_EXACT else M.MLMC_FP32
+    a = M.level_args(M.gbm(), 3, 64, precision, rv_mode, 0, 0, scheme=scheme)
+    assert M.mlmc_level_workspace_bytes(a) == 0
+    assert M.lib().mlmc_paths(ctypes.byref(a), None, None, None, None, None, None) == M.MLMC_EINVAL
+    assert "scheme" in M.mlmc_last_error().lower() or "milstein" in M.mlmc_last_error().lower()
 
 
 @pytest.mark.parametrize("sde", [M.gbm(T=0.0), M.gbm(sigma=-1.0), M.gbm(payoff=7), M.gbm(mu=float("nan"))])
@@ -75,10 +86,11 @@ def test_null_pointers_rejected():
 
 
 def test_workspace_size():
+    # chunk partials (8 doubles per chunk), 128 stage rows of the reduction, its counter
     args = M.level_args(M.gbm(), 5, 1000, M.MLMC_FP32, M.MLMC_NESTED_PWL16)
-    assert M.mlmc_level_workspace_bytes(args) == 16 * 8 * 8     # 16 chunks of 64 paths
+    assert M.mlmc_level_workspace_bytes(args) == (16 + 128) * 8 * 8 + 64     # 16 chunks of 64 paths
     args16 = M.level_args(M.gbm(), 5, 1000, M.MLMC_FP16, M.MLMC_NESTED_PWL16)
-    assert M.mlmc_level_workspace_bytes(args16) == 8 * 8 * 8    # 8 chunks of 128 paths
+    assert M.mlmc_level_workspace_bytes(args16) == (8 + 128) * 8 * 8 + 64    # 8 chunks of 128 paths
 
 
 @pytest.mark.skipif(_gpu_visible(), reason="a GPU is visible")
@@ -97,6 +109,8 @@ def test_library_table_matches_oracle_table(rv, deg):
     assert np.max(np.abs(got - want) / np.abs(want)) < 1e-12
     for p, dt in ((M.MLMC_FP32, np.float32), (M.MLMC_FP16, np.float16)):
         np.testing.assert_array_equal(np.array(M.mlmc_table(rv, p))[:, :deg + 1], want.astype(dt).astype(np.float64))
+    # bfloat16: one rounding of the binary64 coefficients to 8 significant bits
+    np.testing.assert_array_equal(np.array(M.mlmc_table(rv, M.MLMC_BF16))[:, :deg + 1], fp.round_bits(want, 8))
 
 
 def test_batch_validation_before_device():
