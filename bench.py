@@ -50,9 +50,10 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 ALG_OPS_PER_STEP = 59.0
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (89.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "2c24cb07275c4c92c9bd7897c2afc0ca2f150be01d269daf6a72892efc0f6417"
-KERNEL_SOURCES = ("level_kernel.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip", "icdf_exact_coeffs.h")
+TRAFFIC_BYTES_PER_LAUNCH = (93.0 * 2.0 + 1024.03125) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "79a97785dbb40fb90754ffe1231c7876144ea438a06e04c0f31a932c25250ff8"
+KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
+                  "icdf_exact_coeffs.h")
 
 
 def kernel_sources_sha256():
@@ -376,6 +377,36 @@ def reports(M, E, torch):
         "plain_fp64_estimate": plain["estimate"], "plain_fp64_std_error": plain["std_error"],
         "plain_fp64_measured_device_seconds": plain["measured_seconds"],
         "measured_speedup_vs_fp64": plain["measured_seconds"] / mixed["measured_seconds"]}
+
+    # Milstein (Section 4: order-1 strong convergence moves the work to the coarse levels):
+    # plain binary64 level variances against Euler-Maruyama's, nested rates, and the adaptive
+    # precision map at the same accuracy
+    mil = {}
+    lv = list(range(0, 11))
+    for tag, sch in (("em", M.MLMC_SCHEME_EM), ("milstein", M.MLMC_SCHEME_MILSTEIN)):
+        rows = [M.mlmc_level_run(M.level_args(call, l, 2 ** 20, M.MLMC_FP64, M.MLMC_EXACT, 0, SEED, scheme=sch))
+                for l in lv]
+        mil["plain_fp64_var_" + tag] = var(rows, 0)
+    for tag, prec, mode, k in (("nested_fp32_pwl", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0),
+                               ("nested_fp16_cubic_kahan", M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1),
+                               ("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0)):
+        a = M.level_args(call, 10, 2 ** 20, prec, mode, k, SEED, scheme=M.MLMC_SCHEME_MILSTEIN)
+        M.mlmc_level_run(a)
+        r = M.mlmc_level_run(a)
+        mil["level10_path_steps_per_s_" + tag] = r["path_steps"] / r["cost_seconds"]
+    mil["levels"] = lv
+    m_mixed = D.adaptive_mlmc(call, 1e-5, seed=23, scheme=M.MLMC_SCHEME_MILSTEIN)
+    m_plain = D.adaptive_mlmc(call, 1e-5, options=(D.PLAIN_FP64,), seed=23, scheme=M.MLMC_SCHEME_MILSTEIN)
+    mil["adaptive_call_eps1e-5"] = {
+        "estimate": m_mixed["estimate"], "std_error": m_mixed["std_error"], "L": m_mixed["L"],
+        "choice": m_mixed["choice"],
+        "predicted_speedup_vs_fp64": m_mixed["predicted_seconds_single_option"]["fp64"]
+        / m_mixed["predicted_seconds"],
+        "measured_device_seconds": m_mixed["measured_seconds"],
+        "plain_fp64_estimate": m_plain["estimate"], "plain_fp64_measured_device_seconds": m_plain["measured_seconds"],
+        "measured_speedup_vs_fp64": m_plain["measured_seconds"] / m_mixed["measured_seconds"],
+        "em_plain_fp64_measured_device_seconds": plain["measured_seconds"]}
+    rep["milstein_call"] = mil
     np.seterr(all="ignore")
     return rep
 

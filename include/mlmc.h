@@ -154,6 +154,11 @@ int mlmc_shutdown(void);
 int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision,
                int rv_mode, int kahan, uint64_t seed, mlmc_result_t* out);
 
+/* mlmc_level with the full argument set (any scheme, stream, pset, path_offset, diag):
+ * args, out: host.  Synchronous on the library's stream; out receives the sums and the
+ * device time of the call.  Errors as mlmc_level. */
+int mlmc_level_run(const mlmc_level_args_t* args, mlmc_result_t* out);
+
 /* Asynchronous level call on hip_stream.  args: host.  d_out: device, 8 doubles
  * (sum[0..3], sumsq[0..3]) written when the stream reaches the call.  d_workspace:
  * device scratch of at least mlmc_level_workspace_bytes(args) bytes (8-byte aligned; it

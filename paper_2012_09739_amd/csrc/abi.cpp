@@ -481,33 +481,18 @@ int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspac
                          (hipStream_t)hip_stream);
 }
 
-int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision, int rv_mode, int kahan,
-               uint64_t seed, mlmc_result_t* out) {
-    if (!sde) return fail(MLMC_EINVAL, "sde is NULL");
+int mlmc_level_run(const mlmc_level_args_t* args, mlmc_result_t* out) {
     if (!out) return fail(MLMC_EINVAL, "out is NULL");
-    mlmc_level_args_t a;
-    std::memset(&a, 0, sizeof a);
-    a.sde = *sde;
-    a.level = level;
-    a.precision = precision;
-    a.rv_mode = rv_mode;
-    a.kahan = kahan;
-    a.diag = 0;
-    a.stream = rv_mode >= MLMC_NESTED_PWL16 ? 1u : 0u;
-    a.pset = 0;
-    a.seed = seed;
-    a.n_paths = n_paths;
-    a.path_offset = 0;
     Variant v;
-    int rc = validate_args(&a, &v);
+    int rc = validate_args(args, &v);
     if (rc) return rc;
     DevState* st;
     if ((rc = device_state(&st))) return rc;
-    const size_t need = level_workspace_bytes(n_chunks_of(&a));
+    const size_t need = level_workspace_bytes(n_chunks_of(args));
     if ((rc = ensure_scratch(*st, need))) return rc;
     hipError_t e = hipEventRecord(st->ev0, st->stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    rc = enqueue_level(*st, &a, v, st->out8, st->scratch, nullptr, nullptr, nullptr, nullptr, nullptr, st->stream);
+    rc = enqueue_level(*st, args, v, st->out8, st->scratch, nullptr, nullptr, nullptr, nullptr, nullptr, st->stream);
     if (rc) return rc;
     if ((e = hipEventRecord(st->ev1, st->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     double h[kPartial];
@@ -522,10 +507,28 @@ int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision
         out->sum[k] = m[k] ? h[k] : NAN;
         out->sumsq[k] = m[k] ? h[kTerms + k] : NAN;
     }
-    out->n_paths = n_paths;
-    out->path_steps = n_paths << level;
+    out->n_paths = args->n_paths;
+    out->path_steps = args->n_paths << args->level;
     out->cost_seconds = 1e-3 * (double)ms;
     return MLMC_OK;
+}
+
+int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision, int rv_mode, int kahan,
+               uint64_t seed, mlmc_result_t* out) {
+    if (!sde) return fail(MLMC_EINVAL, "sde is NULL");
+    if (!out) return fail(MLMC_EINVAL, "out is NULL");
+    mlmc_level_args_t a;
+    std::memset(&a, 0, sizeof a);
+    a.sde = *sde;
+    a.level = level;
+    a.precision = precision;
+    a.rv_mode = rv_mode;
+    a.kahan = kahan;
+    a.stream = rv_mode >= MLMC_NESTED_PWL16 ? 1u : 0u;
+    a.seed = seed;
+    a.n_paths = n_paths;
+    a.scheme = MLMC_SCHEME_EM;
+    return mlmc_level_run(&a, out);
 }
 
 int mlmc_paths(const mlmc_level_args_t* args, double* d_pf_hat, double* d_pc_hat, double* d_pf_bar,

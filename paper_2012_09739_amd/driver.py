@@ -14,9 +14,12 @@ squared error eps^2 (variance eps^2 / 2, bias at most eps / sqrt 2) is
 smallest a_l.  The number of samples of each term j is m_j = 2 eps^-2 sqrt(v_j / c_j)
 sum_k sqrt(v_k c_k) over all terms of all levels.
 
-Levels are added until Giles' weak-error test holds: with alpha = 1 (Euler-Maruyama),
-max(|E d_L|, |E d_{L-1}| / 2) / (2^alpha - 1) <= eps / sqrt 2, d_l the exact two-way
-difference.  Every sample comes from the level calls of the C-ABI; the arithmetic here
+Levels are added until Giles' weak-error test holds: with alpha = 1 (the weak order of
+both Euler-Maruyama and Milstein), max(|E d_L|, |E d_{L-1}| / 2) / (2^alpha - 1) <= eps / sqrt 2,
+d_l the exact two-way difference.  Every level of one run uses the same scheme; with
+Milstein (order-1 strong convergence) the level variances fall as 4^-l instead of 2^-l and
+the work moves to the coarse levels, where the low-precision options are cheapest
+(Section 4).  Every sample comes from the level calls of the C-ABI; the arithmetic here
 is on a few numbers per level.  Pilot and final samples use different Philox keys.
 """
 
@@ -105,24 +108,29 @@ def _marginal(call, n):
     return r2, max(extra, 0.05 * r2["cost_seconds"]) / n
 
 
-def pilot_level(sde, level, options, n, seed):
+def _level(sde, level, n, precision, rv_mode, kahan, seed, scheme):
+    """One synchronous level call (Philox stream 1 for nested modes, 0 otherwise)."""
+    return M.mlmc_level_run(M.level_args(sde, level, n, precision, rv_mode, kahan, seed, scheme=scheme))
+
+
+def pilot_level(sde, level, options, n, seed, scheme=M.MLMC_SCHEME_EM):
     """Pilot runs of every option at one level: variances from 2n samples, device costs per
     sample as marginal costs (after a warm call, so that no first-launch cost enters)."""
     p = LevelPilot(level)
     for opt in options:
         if not opt.nested:
-            M.mlmc_level(sde, level, 1024, opt.precision, M.MLMC_EXACT, 0, seed)
-            r, c = _marginal(lambda k: M.mlmc_level(sde, level, k, opt.precision, M.MLMC_EXACT, 0, seed), n)
+            _level(sde, level, 1024, opt.precision, M.MLMC_EXACT, 0, seed, scheme)
+            r, c = _marginal(lambda k: _level(sde, level, k, opt.precision, M.MLMC_EXACT, 0, seed, scheme), n)
             m, v = _stats(r, 0)
             p.terms[opt.name] = [(v, c)]
             p.mean_exact = m
         else:
             approx, nested = opt.rv, opt.rv + 4
-            M.mlmc_level(sde, level, 1024, opt.precision, approx, opt.kahan, seed)
-            M.mlmc_level(sde, level, 1024, opt.precision, nested, opt.kahan, seed)
-            r, c = _marginal(lambda k: M.mlmc_level(sde, level, k, opt.precision, approx, opt.kahan, seed), n)
+            _level(sde, level, 1024, opt.precision, approx, opt.kahan, seed, scheme)
+            _level(sde, level, 1024, opt.precision, nested, opt.kahan, seed, scheme)
+            r, c = _marginal(lambda k: _level(sde, level, k, opt.precision, approx, opt.kahan, seed, scheme), n)
             _, v = _stats(r, 0)
-            r, C = _marginal(lambda k: M.mlmc_level(sde, level, k, opt.precision, nested, opt.kahan, seed), n)
+            r, C = _marginal(lambda k: _level(sde, level, k, opt.precision, nested, opt.kahan, seed, scheme), n)
             _, V = _stats(r, 1)
             p.terms[opt.name] = [(v, c), (V, C)]
             if not any(not o.nested for o in options):
@@ -130,22 +138,22 @@ def pilot_level(sde, level, options, n, seed):
     return p
 
 
-def _run_term(sde, level, opt, term_index, n, seed):
+def _run_term(sde, level, opt, term_index, n, seed, scheme=M.MLMC_SCHEME_EM):
     """n samples of one term of one option; returns (sum, sum of squares, n, device seconds)."""
     if not opt.nested:
-        r = M.mlmc_level(sde, level, n, opt.precision, M.MLMC_EXACT, 0, seed)
+        r = _level(sde, level, n, opt.precision, M.MLMC_EXACT, 0, seed, scheme)
         t = 0
     elif term_index == 0:
-        r = M.mlmc_level(sde, level, n, opt.precision, opt.rv, opt.kahan, seed)
+        r = _level(sde, level, n, opt.precision, opt.rv, opt.kahan, seed, scheme)
         t = 0
     else:
-        r = M.mlmc_level(sde, level, n, opt.precision, opt.rv + 4, opt.kahan, seed)
+        r = _level(sde, level, n, opt.precision, opt.rv + 4, opt.kahan, seed, scheme)
         t = 1
     return r["sum"][t], r["sumsq"][t], n, r["cost_seconds"]
 
 
 def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pilot=2 ** 19, seed=0,
-                  max_samples=2 ** 32):
+                  max_samples=2 ** 32, scheme=M.MLMC_SCHEME_EM):
     """Adaptive MLMC to root-mean-square error eps with a per-level choice among options.
 
     Returns a dict: estimate, its standard error, L, per-level choice, samples per term,
@@ -157,7 +165,7 @@ def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pil
     pilots = []
     level = 0
     while True:
-        pilots.append(pilot_level(sde, level, options, n_pilot, seed))
+        pilots.append(pilot_level(sde, level, options, n_pilot, seed, scheme))
         if level >= l_min and weak_converged([p.mean_exact for p in pilots], eps):
             break
         if level == l_max:
@@ -177,7 +185,7 @@ def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pil
     sums = {}
     device_s = 0.0
     for (l, name, j), n in zip(where, counts):
-        s, q, m, t = _run_term(sde, l, by_name[name], j, n, final_seed)
+        s, q, m, t = _run_term(sde, l, by_name[name], j, n, final_seed, scheme)
         sums[(l, j)] = (s, q, m)
         device_s += t
     estimate, var = 0.0, 0.0

@@ -74,6 +74,7 @@ _SIGNATURES = {
     "mlmc_shutdown": (ctypes.c_int, []),
     "mlmc_level": (ctypes.c_int, [ctypes.POINTER(mlmc_gbm_t), ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(mlmc_result_t)]),
+    "mlmc_level_run": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), ctypes.POINTER(mlmc_result_t)]),
     "mlmc_level_ex": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), _P, _P, ctypes.c_size_t, _P]),
     "mlmc_level_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(mlmc_level_args_t)]),
     "mlmc_paths": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), _P, _P, _P, _P, _P, _P]),
@@ -173,6 +174,13 @@ def mlmc_level(sde, level, n_paths, precision, rv_mode, kahan, seed):
     out = mlmc_result_t()
     _check(lib().mlmc_level(ctypes.byref(sde), level, n_paths, precision, rv_mode, int(kahan), seed,
                             ctypes.byref(out)))
+    return _result_dict(out)
+
+
+def mlmc_level_run(args):
+    """Synchronous level call with the full argument set; returns the same dict as mlmc_level."""
+    out = mlmc_result_t()
+    _check(lib().mlmc_level_run(ctypes.byref(args), ctypes.byref(out)))
     return _result_dict(out)
 
 

@@ -41,11 +41,12 @@ def test_weak_error_test(K, eps, L_expected):
 
 
 class FakeLevels:
-    """Stands in for mlmc_level: sums of n samples equal n * mean and the sums of squares
+    """Stands in for mlmc_level_run: sums of n samples equal n * mean and the sums of squares
     n * (var + mean^2), so level_stats returns the prescribed mean and (n/(n-1)) var."""
 
     def __init__(self, mu=0.05):
         self.calls = []
+        self.schemes = set()
         self.mu = mu
 
     def moments(self, level, precision, mode):
@@ -59,7 +60,10 @@ class FakeLevels:
             return [(d * 0.99, v_exact)], base
         return [(d * 0.99, v_exact), (d * 0.01, 1e-8 * 2.0 ** -level), (d, v_exact)], base + 8e-9 * 2 ** level
 
-    def __call__(self, sde, level, n, precision, mode, kahan, seed):
+    def __call__(self, args):
+        level, n, precision, mode = args.level, args.n_paths, args.precision, args.rv_mode
+        kahan, seed = args.kahan, args.seed
+        self.schemes.add(args.scheme)
         self.calls.append((level, n, precision, mode, kahan, seed))
         terms, c = self.moments(level, precision, mode)
         s, q = [math.nan] * 4, [math.nan] * 4
@@ -71,9 +75,9 @@ class FakeLevels:
 
 def test_driver_orchestration_with_synthetic_levels(monkeypatch):
     fake = FakeLevels()
-    monkeypatch.setattr(D.M, "mlmc_level", fake)
+    monkeypatch.setattr(D.M, "mlmc_level_run", fake)
     eps = 1e-3
-    out = D.adaptive_mlmc(None, eps, n_pilot=1 << 16)
+    out = D.adaptive_mlmc(M.gbm(), eps, n_pilot=1 << 16)
     L = out["L"]
     assert L == 4                                     # 1e-2 2^-L <= eps / sqrt 2
     # the estimate is the sum of the prescribed level means whatever the choice per level
@@ -89,3 +93,11 @@ def test_driver_orchestration_with_synthetic_levels(monkeypatch):
     # pilot and final samples use different Philox keys
     assert {c[-1] for c in fake.calls} == {0, 1}
     assert out["std_error"] <= eps / math.sqrt(2) * 1.01
+    assert fake.schemes == {M.MLMC_SCHEME_EM}
+
+
+def test_driver_passes_the_scheme_to_every_call(monkeypatch):
+    fake = FakeLevels()
+    monkeypatch.setattr(D.M, "mlmc_level_run", fake)
+    D.adaptive_mlmc(M.gbm(), 1e-3, n_pilot=1 << 10, scheme=M.MLMC_SCHEME_MILSTEIN)
+    assert fake.schemes == {M.MLMC_SCHEME_MILSTEIN}

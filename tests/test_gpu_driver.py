@@ -2,7 +2,9 @@
 with exact variables has E[X_N] = X0 (1 + mu 2^-L)^(2^L) exactly (binary64 rounding aside),
 and every per-level option (plain binary64, or nested binary32 / binary16 with the four-way
 correction) has the same expectation, so the mixed estimator must land within a few
-standard errors of that value."""
+standard errors of that value.  The Milstein factor 1 + mu delta + sigma dW +
+sigma^2 (dW^2 - delta) / 2 has the same expectation 1 + mu delta, so the same value holds for
+the Milstein levels."""
 
 import math
 
@@ -34,3 +36,13 @@ def test_plain_only_driver_matches_the_same_value():
     exact = (1.0 + 0.05 * 2.0 ** -L) ** (2 ** L)
     assert set(out["choice"]) == {"fp64"}
     assert abs(out["estimate"] - exact) <= 4.0 * out["std_error"]
+
+
+def test_milstein_adaptive_mixture_is_unbiased():
+    eps = 1e-4
+    out = D.adaptive_mlmc(M.gbm(), eps, n_pilot=1 << 16, seed=13, scheme=M.MLMC_SCHEME_MILSTEIN)
+    L = out["L"]
+    exact = (1.0 + 0.05 * 2.0 ** -L) ** (2 ** L)
+    assert abs(out["estimate"] - exact) <= 4.0 * out["std_error"], (out["estimate"], exact, out["std_error"])
+    assert out["std_error"] <= eps / math.sqrt(2) * 1.25
+    assert out["predicted_seconds"] <= min(out["predicted_seconds_single_option"].values()) * (1 + 1e-12)
