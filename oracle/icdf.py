@@ -23,6 +23,11 @@ Word-to-interval map (the build's reading of the dyadic construction; u = (x + 1
     Z~ = s ? -q_j(t) : q_j(t)
 The local coordinate is exact in float64; precision p uses R_p(t), except binary16 which
 uses R_16(R_32(t)) (the coordinate is formed in binary32 and then narrowed).
+
+``approx`` with RV_PCONST: the piecewise-constant variable of ``oracle.tables.pconst`` on
+2^b equal cells (b = 12): with s and x' as above, cell i = x' >> (32 - b) of the lower half
+(the cell of u' = (x' + 1/2) 2^-32, since the cells are aligned to the word grid) and
+Z~ = s ? -m_i : m_i, m_i the cell mean rounded once to precision p.  No arithmetic.
 """
 
 import numpy as np
@@ -31,7 +36,7 @@ from scipy.special import ndtri
 from . import fp
 from . import tables as _tables
 
-RV_PWL, RV_CUBIC = 1, 2
+RV_PWL, RV_CUBIC, RV_PCONST = 1, 2, 4
 _DEGREE = {RV_PWL: 1, RV_CUBIC: 3}
 
 
@@ -75,8 +80,20 @@ def local_coordinate(t, precision):
     return fp.rn(precision, t)
 
 
+def pconst_cell(x, bits=_tables.PC_BITS):
+    """(sign_flag, lower-half cell index) of uint32 word(s) x on 2^bits equal cells."""
+    x = np.asarray(x, dtype=np.uint64)
+    s = x >= np.uint64(2 ** 31)
+    xm = np.where(s, np.uint64(2 ** 32 - 1) - x, x)
+    return s, (xm >> np.uint64(32 - bits)).astype(np.int64)
+
+
 def approx(x, rv_mode, precision):
     """Z~ = Phi~^{-1}(U) in precision p for uint32 word(s) x (Section 2.1, Lemmas 2.2/2.3)."""
+    if rv_mode == RV_PCONST:
+        s, i = pconst_cell(x)
+        m = fp.rn(precision, np.array(_tables.pconst(), dtype=np.float64))[i]
+        return fp.like(m, np.where(s, -fp.to64(m), fp.to64(m)))
     s, j, t = locate(x)
     c = coefficients(rv_mode, precision)[j - 1]          # rows of (c_0..c_d), dtype p
     tp = local_coordinate(t, precision)

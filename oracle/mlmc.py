@@ -43,7 +43,7 @@ import numpy as np
 from . import fp, icdf, philox
 from . import mlp as _mlp
 
-RV_EXACT, RV_PWL, RV_CUBIC, RV_MLP = 0, 1, 2, 3
+RV_EXACT, RV_PWL, RV_CUBIC, RV_MLP, RV_PCONST = 0, 1, 2, 3, 4
 SCHEME_EM, SCHEME_MILSTEIN = 0, 1
 PAYOFF_X, PAYOFF_CALL = 0, 1
 TERM_TWO_WAY, TERM_FOUR_WAY, TERM_TWO_WAY_EXACT, TERM_ROUNDING = 0, 1, 2, 3

@@ -24,6 +24,17 @@ Pinned by ``tests/test_oracle_tables.py``: a dense-grid weighted least-squares f
 NumPy (an independent discretisation of the same minimisation) reproduces the
 coefficients, the residual is orthogonal to 1, t, ..., t^d, and the stored table equals a
 fresh computation.
+
+A further approximate variable (Section 2.1 names table lookups and the Rademacher
+variables of the weak Euler-Maruyama scheme among the substitutes for Z): the
+piecewise-constant inverse CDF on 2^b equal cells of (0, 1), cell i = [i 2^-b, (i+1) 2^-b),
+whose value is the cell mean of Phi^{-1} -- the L2-optimal constant, i.e. Z~ = E[Z | cell]:
+
+    mean_i = 2^b int_a^b' Phi^{-1}(u) du = 2^b (phi(Phi^{-1}(a)) - phi(Phi^{-1}(b')))
+
+(substitute u = Phi(z): int z phi(z) dz = -phi(z)).  Only the lower half (i < 2^(b-1)) is
+stored; the upper half is its mirror.  b = 1 gives the two-point variable +-sqrt(2/pi).
+Pinned by ``tests/test_oracle_pconst.py``.
 """
 
 import functools
@@ -99,3 +110,31 @@ def table(degree):
         if key in stored:
             return tuple(tuple(float.fromhex(h) for h in row) for row in stored[key]["coefficients"])
     return compute_table(degree)
+
+
+PC_BITS = 12   # 4096 cells of (0, 1); 2048 stored cell means
+
+
+def compute_pconst(bits=PC_BITS, dps=40):
+    """Fresh mpmath computation of the lower-half cell means (float64), cell i < 2^(bits-1)."""
+    n = 2 ** (bits - 1)
+    with mp.workdps(dps):
+        scale = mp.mpf(2) ** bits
+        dens = [mp.mpf(0)]                   # phi(Phi^{-1}(0)) = 0
+        for i in range(1, n + 1):
+            z = phi_inv_mp(mp.mpf(i) / scale)
+            dens.append(mp.npdf(z))
+        return tuple(float(scale * (dens[i] - dens[i + 1])) for i in range(n))
+
+
+@functools.lru_cache(maxsize=None)
+def pconst(bits=PC_BITS):
+    """The float64 lower-half cell means of the piecewise-constant inverse CDF; the stored
+    copy written by ``tests/golden/make_golden.py`` when present, else computed."""
+    key = "pconst%d" % (2 ** bits)
+    if os.path.exists(_STORED):
+        with open(_STORED) as fh:
+            stored = json.load(fh)
+        if key in stored:
+            return tuple(float.fromhex(h) for h in stored[key]["means"])
+    return compute_pconst(bits)

@@ -6,7 +6,9 @@ It imports nothing but ``oracle`` (and the standard library / NumPy / mpmath).
 * dyadic_tables.json - the float64 master coefficient tables of the piecewise linear and
   piecewise cubic approximations of Phi^{-1} on 16 dyadic intervals of (0, 1/2]
   (Section 2.1, Figure 1, Lemmas 2.2 and 2.3; construction read as independent L2-optimal
-  fits per interval), stored as exact hexadecimal floats.
+  fits per interval), stored as exact hexadecimal floats; and the lower-half cell means of
+  the piecewise-constant inverse CDF on 4096 equal cells of (0, 1) (a table-lookup
+  approximate variable, Section 2.1), likewise.
 """
 
 import json
@@ -32,6 +34,13 @@ def main():
             "degree": degree,
             "coefficients": [[float(c).hex() for c in row] for row in tab],
         }
+    bits = tables.PC_BITS
+    out["pconst%d" % 2 ** bits] = {
+        "citation": "Section 2.1 (approximate random variables by table lookup): the mean of "
+                    "Phi^-1 over each of 2^%d equal cells of (0, 1), lower half" % bits,
+        "bits": bits,
+        "means": [float(m).hex() for m in tables.compute_pconst(bits)],
+    }
     with open(os.path.join(HERE, "dyadic_tables.json"), "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
