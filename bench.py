@@ -50,8 +50,8 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 ALG_OPS_PER_STEP = 59.0
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (93.0 * 2.0 + 1024.03125) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "79a97785dbb40fb90754ffe1231c7876144ea438a06e04c0f31a932c25250ff8"
+TRAFFIC_BYTES_PER_LAUNCH = (90.0 * 2.0 + 1024.03125) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "556e085af83b6151ee161e645b4294959df42d92970033831b81eb07e108f414"
 KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
                   "icdf_exact_coeffs.h")
 
@@ -369,6 +369,12 @@ def reports(M, E, torch):
     from paper_2012_09739_amd import driver as D
     mixed = D.adaptive_mlmc(call, 1e-5, seed=21)
     plain = D.adaptive_mlmc(call, 1e-5, options=(D.PLAIN_FP64,), seed=21)
+    with_pc = D.adaptive_mlmc(call, 1e-5, options=D.TABLE_OPTIONS, seed=21)
+    rep["adaptive_mlmc_call_eps1e-5_with_pconst"] = {
+        "estimate": with_pc["estimate"], "std_error": with_pc["std_error"], "L": with_pc["L"],
+        "choice": with_pc["choice"],
+        "predicted_speedup_vs_fp64": with_pc["predicted_seconds_single_option"]["fp64"] / with_pc["predicted_seconds"],
+        "measured_device_seconds": with_pc["measured_seconds"]}
     rep["adaptive_mlmc_call_eps1e-5"] = {
         "estimate": mixed["estimate"], "std_error": mixed["std_error"], "L": mixed["L"],
         "choice": mixed["choice"], "predicted_speedup_vs_fp64": mixed["predicted_seconds_single_option"]["fp64"]
@@ -407,6 +413,25 @@ def reports(M, E, torch):
         "measured_speedup_vs_fp64": m_plain["measured_seconds"] / m_mixed["measured_seconds"],
         "em_plain_fp64_measured_device_seconds": plain["measured_seconds"]}
     rep["milstein_call"] = mil
+
+    # piecewise-constant variable (4096 cells, table lookup) against the piecewise-linear one:
+    # four-way variances, rates and the equal-variance speed-up over plain binary64 (call,
+    # levels 0..10, 2^20 paths)
+    plain_rows = _level_costs(M, call, LEVELS, N_PATHS, M.MLMC_FP64, M.MLMC_EXACT, 0)
+    pc = {}
+    for tag, prec, approx, nested, k in (
+            ("fp32_pconst", M.MLMC_FP32, M.MLMC_APPROX_PCONST4096, M.MLMC_NESTED_PCONST4096, 0),
+            ("fp32_pwl16", M.MLMC_FP32, M.MLMC_APPROX_PWL16, M.MLMC_NESTED_PWL16, 0),
+            ("fp16_pconst_kahan", M.MLMC_FP16, M.MLMC_APPROX_PCONST4096, M.MLMC_NESTED_PCONST4096, 1),
+            ("fp16_cubic16_kahan", M.MLMC_FP16, M.MLMC_APPROX_CUBIC16, M.MLMC_NESTED_CUBIC16, 1)):
+        a_rows = _level_costs(M, call, LEVELS, N_PATHS, prec, approx, k)
+        n_rows = _level_costs(M, call, LEVELS, N_PATHS, prec, nested, k)
+        pc[tag] = {"approx_two_way_path_steps_per_s": rate(a_rows), "nested_path_steps_per_s": rate(n_rows),
+                   "four_way_var": var(n_rows, 1),
+                   "speedup_T_hat_over_T_bar": E.speedup_equal_variance(
+                       var(plain_rows, 0), cost(plain_rows), var(a_rows, 0), cost(a_rows), var(n_rows, 1),
+                       cost(n_rows))}
+    rep["pconst4096_vs_dyadic_call_levels0to10_2p20"] = pc
     np.seterr(all="ignore")
     return rep
 

@@ -57,7 +57,7 @@ extern "C" {
 #define MLMC_FP16 2 /* packed half2: two paths per lane */
 /* bfloat16 (8 significant bits, the binary32 exponent range), emulated: binary32 registers,
  * every operation rounded to 8 bits, to nearest even; approximate and nested modes with
- * the dyadic tables only (the precision-width experiments around Figure 3) */
+ * the table approximations only (the precision-width experiments around Figure 3) */
 #define MLMC_BF16 3
 
 /* inverse-CDF kind (Section 2.1; 16 dyadic intervals of (0,1/2], mirrored) */
@@ -65,6 +65,10 @@ extern "C" {
 #define MLMC_RV_PWL16 1   /* piecewise linear, L2-optimal per interval (Lemma 2.2)     */
 #define MLMC_RV_CUBIC16 2 /* piecewise cubic, L2-optimal per interval (Lemma 2.3)      */
 #define MLMC_RV_MLP 3     /* 1-16-16-1 tanh network (binary16 weights), mirrored        */
+#define MLMC_RV_PCONST4096 4 /* piecewise constant by table lookup (Section 2.1 names   */
+                             /* table lookups among the substitutes for Z): the mean of */
+                             /* Phi^-1 on each of 4096 equal cells of (0,1), mirrored;  */
+                             /* cell = top 12 bits of the mirrored word                */
 
 /* rv_mode of mlmc_level: which differences one call samples (Section 3) */
 #define MLMC_EXACT 0          /* term 0 = P^_l - P^_{l-1}, binary64, exact variables      */
@@ -74,6 +78,8 @@ extern "C" {
 #define MLMC_NESTED_PWL16 5   /* nested: terms 0, 1 (four-way) and 2 on the same samples  */
 #define MLMC_NESTED_CUBIC16 6
 #define MLMC_NESTED_MLP 7
+#define MLMC_APPROX_PCONST4096 4
+#define MLMC_NESTED_PCONST4096 8
 
 /* terms of a result */
 #define MLMC_TERM_TWO_WAY 0       /* two-way difference of the call's own pair            */
@@ -197,6 +203,12 @@ int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double
  * and widened to binary64, written to h_out (host, 16 * 4 doubles; unused columns 0).
  * rv: MLMC_RV_PWL16 or MLMC_RV_CUBIC16.  Host-only: needs no GPU. */
 int mlmc_table(int rv, int precision, double* h_out);
+
+/* Lower-half cell means of MLMC_RV_PCONST4096 (cell i = [i/4096, (i+1)/4096), i < 2048;
+ * the upper half is the mirror) rounded to `precision` and widened to binary64, written to
+ * h_out (host, 2048 doubles).  Built on the host as 4096 (phi(Phi^-1(a)) - phi(Phi^-1(b)))
+ * in long double.  Host-only: needs no GPU. */
+int mlmc_pconst_table(int precision, double* h_out);
 
 /* ---- batched sweep: many (parameter set, level) items in one persistent launch -------
  * Not in the paper: a full MLMC sweep (Section 3: every level l = 0..L, here also many

@@ -16,6 +16,7 @@
 namespace mlmc {
 
 bool build_l2_table(int degree, double out[16][4]);
+bool build_pconst_table(int bits, double* out);
 hipError_t launch_mlp_deploy(const float* d_params, float* image, hipStream_t s);
 hipError_t launch_level_f64(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
 hipError_t launch_level_f32(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
@@ -76,9 +77,13 @@ int hip_fail(hipError_t e, const char* what) {
 struct HostTables {
     double pwl[16][4];
     double cubic[16][4];
+    double pconst[kPcEntries];  // lower-half cell means of the piecewise-constant variable
     bool ok = false;
-    HostTables() { ok = build_l2_table(1, pwl) && build_l2_table(3, cubic); }
+    HostTables() { ok = build_l2_table(1, pwl) && build_l2_table(3, cubic) && build_pconst_table(kPcBits, pconst); }
 };
+
+// value of a binary64 master rounded once to precision p, widened back to binary64
+double rounded_to(int precision, double c);
 
 const HostTables& host_tables() {
     static const HostTables t;
@@ -95,6 +100,13 @@ __half half_of(double d) {
     return h;
 }
 
+double rounded_to(int precision, double c) {
+    if (precision == MLMC_FP32) return (double)(float)c;
+    if (precision == MLMC_FP16) return (double)__half2float(half_of(c));
+    if (precision == MLMC_BF16) return bf16_of(c);
+    return c;
+}
+
 // ---- per-device state -------------------------------------------------------------------
 struct DevState {
     bool ready = false;
@@ -103,6 +115,7 @@ struct DevState {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     void* tables[2][4] = {{nullptr}};  // [pwl, cubic][precision], 16 x (d+1) coefficients
     double* tables64[2] = {nullptr, nullptr};
+    void* pconst[4] = {nullptr};       // [precision], kPcEntries cell means
     double* scratch = nullptr;
     size_t scratch_bytes = 0;
     double* out8 = nullptr;             // result slot of the synchronous entry point
@@ -156,6 +169,26 @@ int upload_tables(DevState& st) {
             (e = hipMemcpy(st.tables[r][MLMC_BF16], hbf, n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
             return hip_fail(e, "hipMemcpy");
         st.tables64[r] = (double*)st.tables[r][MLMC_FP64];
+    }
+    {
+        static double h64[kPcEntries];
+        static float h32[kPcEntries], hbf[kPcEntries];
+        static __half h16[kPcEntries];
+        for (int i = 0; i < kPcEntries; ++i) {
+            const double c = ht.pconst[i];
+            h64[i] = c;
+            h32[i] = (float)c;
+            h16[i] = half_of(c);
+            hbf[i] = (float)bf16_of(c);
+        }
+        const void* src[4] = {h64, h32, h16, hbf};
+        const size_t bytes[4] = {sizeof h64, sizeof h32, sizeof h16, sizeof hbf};
+        for (int q = 0; q < 4; ++q) {
+            hipError_t e;
+            if ((e = hipMalloc(&st.pconst[q], bytes[q])) != hipSuccess) return hip_fail(e, "hipMalloc");
+            if ((e = hipMemcpy(st.pconst[q], src[q], bytes[q], hipMemcpyHostToDevice)) != hipSuccess)
+                return hip_fail(e, "hipMemcpy");
+        }
     }
     return MLMC_OK;
 }
@@ -246,6 +279,8 @@ int rv_of_mode(int rv_mode, int* rv, bool* nested) {
         case MLMC_NESTED_PWL16: *rv = MLMC_RV_PWL16; *nested = true; return MLMC_OK;
         case MLMC_NESTED_CUBIC16: *rv = MLMC_RV_CUBIC16; *nested = true; return MLMC_OK;
         case MLMC_NESTED_MLP: *rv = MLMC_RV_MLP; *nested = true; return MLMC_OK;
+        case MLMC_APPROX_PCONST4096: *rv = MLMC_RV_PCONST4096; *nested = false; return MLMC_OK;
+        case MLMC_NESTED_PCONST4096: *rv = MLMC_RV_PCONST4096; *nested = true; return MLMC_OK;
         default: return fail(MLMC_EINVAL, "rv_mode %d is not a valid MLMC_EXACT/APPROX/NESTED mode", rv_mode);
     }
 }
@@ -271,7 +306,7 @@ int validate_args(const mlmc_level_args_t* a, Variant* v) {
         return fail(MLMC_EINVAL, "MLMC_EXACT (the plain estimator) runs in MLMC_FP64");
     if (rv == MLMC_RV_EXACT && a->diag) return fail(MLMC_EINVAL, "diag needs an approximate rv_mode");
     if (a->precision == MLMC_BF16 && rv == MLMC_RV_MLP)
-        return fail(MLMC_EINVAL, "MLMC_BF16 runs the dyadic approximations (PWL16, CUBIC16) only");
+        return fail(MLMC_EINVAL, "MLMC_BF16 runs the table approximations (PWL16, CUBIC16, PCONST4096) only");
     if (a->scheme != MLMC_SCHEME_EM && a->scheme != MLMC_SCHEME_MILSTEIN)
         return fail(MLMC_EINVAL, "scheme %u is not MLMC_SCHEME_EM/MILSTEIN", a->scheme);
     if (a->scheme == MLMC_SCHEME_MILSTEIN && rv == MLMC_RV_MLP)
@@ -297,6 +332,10 @@ LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevS
         const int r = v.rv == MLMC_RV_PWL16 ? 0 : 1;
         p.table = st.tables[r][v.precision];
         p.table64 = st.tables64[r];
+    }
+    if (v.rv == MLMC_RV_PCONST4096) {
+        p.table = st.pconst[v.precision];
+        p.table64 = (const double*)st.pconst[MLMC_FP64];
     }
     p.mlp = st.mlp;
     p.exact_tab = st.exact_tab;
@@ -403,6 +442,7 @@ int device_info(DeviceInfo* out) {
         for (int q = 0; q < 4; ++q) out->tables[r][q] = st->tables[r][q];
         out->tables64[r] = st->tables64[r];
     }
+    for (int q = 0; q < 4; ++q) out->pconst[q] = st->pconst[q];
     out->mlp = st->mlp;
     out->mlp_loaded = st->mlp_loaded;
     out->exact_tab = st->exact_tab;
@@ -440,6 +480,8 @@ int mlmc_shutdown(void) {
         for (auto& row : st.tables)
             for (void*& t : row)
                 if (t) (void)hipFree(t);
+        for (void*& t : st.pconst)
+            if (t) (void)hipFree(t);
         if (st.scratch) (void)hipFree(st.scratch);
         if (st.out8) (void)hipFree(st.out8);
         if (st.mlp) (void)hipFree(st.mlp);
@@ -562,10 +604,10 @@ int mlmc_uniforms(uint64_t seed, uint32_t stream, int level, uint32_t pset, uint
 
 int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double* d_out, void* hip_stream) {
     if ((!d_words || !d_out) && n > 0) return fail(MLMC_EINVAL, "NULL buffer");
-    if (rv < MLMC_RV_EXACT || rv > MLMC_RV_MLP) return fail(MLMC_EINVAL, "rv %d is not an MLMC_RV_* kind", rv);
+    if (rv < MLMC_RV_EXACT || rv > MLMC_RV_PCONST4096) return fail(MLMC_EINVAL, "rv %d is not an MLMC_RV_* kind", rv);
     if (precision < MLMC_FP64 || precision > MLMC_BF16) return fail(MLMC_EINVAL, "precision %d invalid", precision);
-    if (precision == MLMC_BF16 && rv != MLMC_RV_PWL16 && rv != MLMC_RV_CUBIC16)
-        return fail(MLMC_EINVAL, "MLMC_BF16 is available for the dyadic approximations only");
+    if (precision == MLMC_BF16 && (rv == MLMC_RV_EXACT || rv == MLMC_RV_MLP))
+        return fail(MLMC_EINVAL, "MLMC_BF16 is available for the table approximations only");
     DevState* st;
     int rc = device_state(&st);
     if (rc) return rc;
@@ -574,6 +616,7 @@ int mlmc_icdf(const uint32_t* d_words, uint64_t n, int rv, int precision, double
     if (n == 0) return MLMC_OK;
     const void* table = nullptr;
     if (rv == MLMC_RV_PWL16 || rv == MLMC_RV_CUBIC16) table = st->tables[rv == MLMC_RV_PWL16 ? 0 : 1][precision];
+    if (rv == MLMC_RV_PCONST4096) table = st->pconst[precision];
     hipError_t e = launch_icdf(d_words, n, rv, precision, table, st->mlp, st->exact_tab, d_out,
                                (hipStream_t)hip_stream);
     return e == hipSuccess ? MLMC_OK : hip_fail(e, "icdf kernel launch");
@@ -600,14 +643,16 @@ int mlmc_table(int rv, int precision, double* h_out) {
     const double(*src)[4] = rv == MLMC_RV_PWL16 ? ht.pwl : ht.cubic;
     const int d = degree_of(rv);
     for (int j = 0; j < 16; ++j)
-        for (int i = 0; i < 4; ++i) {
-            const double c = i <= d ? src[j][i] : 0.0;
-            double r = c;
-            if (precision == MLMC_FP32) r = (double)(float)c;
-            if (precision == MLMC_FP16) r = (double)__half2float(half_of(c));
-            if (precision == MLMC_BF16) r = bf16_of(c);
-            h_out[j * 4 + i] = r;
-        }
+        for (int i = 0; i < 4; ++i) h_out[j * 4 + i] = rounded_to(precision, i <= d ? src[j][i] : 0.0);
+    return MLMC_OK;
+}
+
+int mlmc_pconst_table(int precision, double* h_out) {
+    if (!h_out) return fail(MLMC_EINVAL, "h_out is NULL");
+    if (precision < MLMC_FP64 || precision > MLMC_BF16) return fail(MLMC_EINVAL, "precision %d invalid", precision);
+    const HostTables& ht = host_tables();
+    if (!ht.ok) return fail(MLMC_EHIP, "table construction failed");
+    for (int i = 0; i < kPcEntries; ++i) h_out[i] = rounded_to(precision, ht.pconst[i]);
     return MLMC_OK;
 }
 

@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include "icdf_exact_coeffs.h"
+#include "internal.h"
 
 namespace mlmc {
 
@@ -244,6 +245,26 @@ __device__ __forceinline__ __half icdf_dyadic_f16(uint32_t word, const __half* _
         q = __hadd(q, c[i]);
     }
     return p.sign ? __hneg(q) : q;
+}
+
+// ---- piecewise-constant variable (table lookup) ------------------------------------------
+// 2^kPcBits equal cells of (0, 1); row i of the table holds the mean of Phi^-1 over
+// [i 2^-b, (i + 1) 2^-b) for the lower half.  With xm the mirrored word, u' = (xm + 1/2) 2^-32
+// lies in cell xm >> (32 - b) (the cells align with the word grid), and the upper half takes
+// the negated value.  No arithmetic: a shift, a load and a sign.
+__device__ __forceinline__ uint32_t pconst_row(uint32_t word) {
+    const uint32_t xm = word ^ (uint32_t)((int32_t)word >> 31);
+    return xm >> (32 - kPcBits);
+}
+__device__ __forceinline__ float icdf_pconst_f32(uint32_t word, const float* __restrict__ tab) {
+    return apply_sign(tab[pconst_row(word)], word & 0x80000000u);
+}
+__device__ __forceinline__ double icdf_pconst_f64(uint32_t word, const double* __restrict__ tab) {
+    return apply_sign(tab[pconst_row(word)], word & 0x80000000u);
+}
+__device__ __forceinline__ __half icdf_pconst_f16(uint32_t word, const __half* __restrict__ tab) {
+    const __half q = tab[pconst_row(word)];
+    return (word >> 31) ? __hneg(q) : q;
 }
 
 }  // namespace mlmc

@@ -15,6 +15,9 @@ constexpr int kPartial = 2 * kTerms;  // (sum, sum of squares) per term
 constexpr int kWave = 64;
 constexpr int kMaxLevel = 24;
 constexpr int kTableRows = 16;
+// piecewise-constant variable: 2^kPcBits equal cells of (0, 1), the lower half stored
+constexpr int kPcBits = 12;
+constexpr int kPcEntries = 1 << (kPcBits - 1);
 
 // Per-launch parameters of one MLMC level (one parameter set).  Constants are rounded
 // on the host from binary64, once, to the working precision p (R_p(mu delta) etc.).
@@ -33,8 +36,8 @@ struct LevelParams {
     uint32_t key0, key1;   // seed
     uint32_t ctr2;         // (stream << 16) | level
     uint32_t pset;
-    const void* table;     // 16 x (DEG + 1) coefficients in the working precision
-    const double* table64; // 16 x (DEG + 1) binary64 master coefficients (diagnostic)
+    const void* table;     // 16 x (DEG + 1) coefficients (dyadic) or kPcEntries cell means, working precision
+    const double* table64; // the same in binary64 (diagnostic)
     const void* mlp;       // MLP inference image (rv = MLP)
     const void* exact_tab; // ExactTable: log cells and piecewise coefficients (exact inverse CDF)
     double* partials;      // [n_chunks][kPartial] chunk partial sums
@@ -78,6 +81,7 @@ struct DeviceInfo {
     int n_cu;
     const void* tables[2][4];  // [pwl, cubic][precision]
     const double* tables64[2];
+    const void* pconst[4];     // cell means of the piecewise-constant variable, [precision]
     const void* mlp;
     bool mlp_loaded;
     const void* exact_tab;

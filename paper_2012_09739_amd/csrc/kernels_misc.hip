@@ -49,6 +49,10 @@ __global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, cons
         double z;
         if constexpr (RV == MLMC_RV_EXACT) {
             z = icdf_exact_f64(w, ex);
+        } else if constexpr (RV == MLMC_RV_PCONST4096) {
+            if constexpr (PREC == MLMC_FP64) z = icdf_pconst_f64(w, (const double*)table);
+            else if constexpr (PREC == MLMC_FP16) z = (double)__half2float(icdf_pconst_f16(w, (const __half*)table));
+            else z = (double)icdf_pconst_f32(w, (const float*)table);
         } else if constexpr (RV == MLMC_RV_MLP) {
             const float y = icdf_mlp_f32(w, (const float*)mlp, ex->log);
             if constexpr (PREC == MLMC_FP16) z = (double)__half2float(__float2half_rn(y));
@@ -109,6 +113,10 @@ hipError_t launch_icdf(const uint32_t* d_words, uint64_t n, int rv, int precisio
     MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_FP32)
     MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_FP16)
     MLMC_ICDF_CASE(MLMC_RV_CUBIC16, MLMC_BF16)
+    MLMC_ICDF_CASE(MLMC_RV_PCONST4096, MLMC_FP64)
+    MLMC_ICDF_CASE(MLMC_RV_PCONST4096, MLMC_FP32)
+    MLMC_ICDF_CASE(MLMC_RV_PCONST4096, MLMC_FP16)
+    MLMC_ICDF_CASE(MLMC_RV_PCONST4096, MLMC_BF16)
     MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP64)
     MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP32)
     MLMC_ICDF_CASE(MLMC_RV_MLP, MLMC_FP16)

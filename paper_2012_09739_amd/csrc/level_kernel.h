@@ -129,6 +129,9 @@ template <int RV, int DEG, typename T, int PREC = MLMC_FP32>
 __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* mlpw, const LogCell* logtab) {
     if constexpr (RV == MLMC_RV_MLP) {
         return (T)icdf_mlp_f32(w, mlpw, logtab);
+    } else if constexpr (RV == MLMC_RV_PCONST4096) {
+        if constexpr (sizeof(T) == 8) return icdf_pconst_f64(w, (const double*)tab);
+        else return icdf_pconst_f32(w, (const float*)tab);  // binary32, or bfloat16 values held in binary32
     } else if constexpr (PREC == MLMC_BF16) {
         return icdf_dyadic_bf16<DEG>(w, (const float*)tab);
     } else if constexpr (sizeof(T) == 8) {
@@ -241,6 +244,9 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
                 if constexpr (RV == MLMC_RV_MLP) {
                     z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw, s_ex->log));
                     z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw, s_ex->log));
+                } else if constexpr (RV == MLMC_RV_PCONST4096) {
+                    z0 = icdf_pconst_f16(r[0].w[i], s_tab16);
+                    z1 = icdf_pconst_f16(r[1].w[i], s_tab16);
                 } else {
                     z0 = icdf_dyadic_f16<DEG>(r[0].w[i], s_tab16);
                     z1 = icdf_dyadic_f16<DEG>(r[1].w[i], s_tab16);
@@ -260,6 +266,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
                 for (int l = 0; l < L; ++l) {
                     double zt;
                     if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw, s_ex->log);
+                    else if constexpr (RV == MLMC_RV_PCONST4096) zt = icdf_pconst_f64(r[l].w[i], s_tab64);
                     else zt = icdf_dyadic_f64<DEG>(r[l].w[i], s_tab64);
                     em_step<SCHEME, double>(Xft[l], zt, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
                 }
@@ -341,13 +348,17 @@ template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = fal
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == MLMC_FP32 || PREC == MLMC_FP64) && RV != MLMC_RV_MLP ? 7 : 1))) void level_kernel(const LevelParams prm) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
+    constexpr bool kPconst = (RV == MLMC_RV_PCONST4096);
     constexpr int L = (PREC == MLMC_FP16) ? 2 : 1;
     using AT = typename std::conditional<PREC == MLMC_FP64, double, float>::type;
 
-    // coefficient tables in LDS (working precision, and binary64 for the diagnostic)
-    __shared__ AT s_tab[kTableRows * 4];
-    __shared__ __half s_tab16[kTableRows * 4];
-    __shared__ double s_tab64[kTableRows * 4];
+    // coefficient tables or cell means in LDS (working precision, and binary64 for the
+    // diagnostic), each sized for the variant that reads it
+    constexpr int kTabN = kPconst ? kPcEntries : kTableRows * (DEG + 1);
+    constexpr bool kTab16 = PREC == MLMC_FP16 && (kDyadic || kPconst);
+    __shared__ AT s_tab[(kDyadic || kPconst) && !kTab16 ? kTabN : 1];
+    __shared__ __half s_tab16[kTab16 ? kTabN : 1];
+    __shared__ double s_tab64[(kDyadic || kPconst) && DIAG ? kTabN : 1];
     __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
     constexpr bool kNeedLog = RV == MLMC_RV_EXACT || NESTED || RV == MLMC_RV_MLP;
     // arm the ticket counter of the reduction that follows this kernel on the stream
@@ -359,10 +370,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == ML
         __syncthreads();
     }
     if constexpr (kDyadic) {
-        for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
+        for (int i = threadIdx.x; i < kTabN; i += blockDim.x) {
             if constexpr (PREC == MLMC_FP16) s_tab16[i] = ((const __half*)prm.table)[i];
             else if constexpr (PREC == MLMC_FP32) s_tab[i] = prescaled_coeff(((const float*)prm.table)[i], i % (DEG + 1));
             else if constexpr (PREC == MLMC_BF16) s_tab[i] = ((const float*)prm.table)[i];  // bfloat16 values, unscaled
+            else s_tab[i] = ((const AT*)prm.table)[i];
+            if constexpr (DIAG) s_tab64[i] = prm.table64[i];
+        }
+        __syncthreads();
+    }
+    if constexpr (kPconst) {
+        for (int i = threadIdx.x; i < kTabN; i += blockDim.x) {
+            if constexpr (PREC == MLMC_FP16) s_tab16[i] = ((const __half*)prm.table)[i];
             else s_tab[i] = ((const AT*)prm.table)[i];
             if constexpr (DIAG) s_tab64[i] = prm.table64[i];
         }

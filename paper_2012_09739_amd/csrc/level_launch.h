@@ -49,6 +49,7 @@ hipError_t launch_level_for(const Variant& v, const LevelParams& p, int grid, in
             return hipErrorInvalidValue;
         case MLMC_RV_PWL16: return by_flags<PREC, SCHEME, MLMC_RV_PWL16>(v, p, grid, block, s);
         case MLMC_RV_CUBIC16: return by_flags<PREC, SCHEME, MLMC_RV_CUBIC16>(v, p, grid, block, s);
+        case MLMC_RV_PCONST4096: return by_flags<PREC, SCHEME, MLMC_RV_PCONST4096>(v, p, grid, block, s);
         case MLMC_RV_MLP:
             if constexpr (kWithMlp) return by_flags<PREC, SCHEME, MLMC_RV_MLP>(v, p, grid, block, s);
             return hipErrorInvalidValue;

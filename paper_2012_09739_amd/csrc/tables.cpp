@@ -140,4 +140,26 @@ bool build_l2_table(int degree, double out[16][4]) {
     return true;
 }
 
+// Cell means of Phi^{-1} on 2^bits equal cells of (0, 1), lower half (n = 2^(bits-1) cells):
+// with u = Phi(z), int_a^b Phi^{-1}(u) du = phi(Phi^{-1}(a)) - phi(Phi^{-1}(b)), so the mean
+// of cell [a, b) is 2^bits (phi(z_a) - phi(z_b)).  The difference is formed without
+// cancellation as phi(z_b) expm1((z_b - z_a)(z_b + z_a) / 2); phi(z_0) = 0 at a = 0 and
+// z = 0 at b = 1/2.  Returns false on a numerical failure (never expected).
+bool build_pconst_table(int bits, double* out) {
+    if (bits < 1 || bits > 20) return false;
+    const int n = 1 << (bits - 1);
+    const long double scale = std::ldexp(1.0L, bits);
+    const long double rsqrt2pi = 0.398942280401432677939946059934381868L;
+    long double za = 0;  // Phi^{-1} of the cell's lower end (unused for the first cell)
+    for (int i = 0; i < n; ++i) {
+        const long double zb = (i + 1 == n) ? 0.0L : phi_inv_ld((i + 1) / scale);
+        const long double pb = rsqrt2pi * std::exp(-0.5L * zb * zb);
+        const long double diff = i == 0 ? -pb : pb * std::expm1(0.5L * (zb - za) * (zb + za));
+        out[i] = (double)(scale * diff);
+        if (!std::isfinite(out[i])) return false;
+        za = zb;
+    }
+    return true;
+}
+
 }  // namespace mlmc

@@ -49,7 +49,10 @@ PLAIN_FP64 = Option("fp64", M.MLMC_FP64)
 NESTED_FP32 = Option("fp32-pwl", M.MLMC_FP32, M.MLMC_RV_PWL16, 0)
 NESTED_FP32_KAHAN = Option("fp32-pwl-kahan", M.MLMC_FP32, M.MLMC_RV_PWL16, 1)
 NESTED_FP16_KAHAN = Option("fp16-cubic-kahan", M.MLMC_FP16, M.MLMC_RV_CUBIC16, 1)
+NESTED_FP32_PCONST = Option("fp32-pconst", M.MLMC_FP32, M.MLMC_RV_PCONST4096, 0)
+NESTED_FP16_PCONST_KAHAN = Option("fp16-pconst-kahan", M.MLMC_FP16, M.MLMC_RV_PCONST4096, 1)
 DEFAULT_OPTIONS = (PLAIN_FP64, NESTED_FP32, NESTED_FP32_KAHAN, NESTED_FP16_KAHAN)
+TABLE_OPTIONS = DEFAULT_OPTIONS + (NESTED_FP32_PCONST, NESTED_FP16_PCONST_KAHAN)
 
 
 @dataclass

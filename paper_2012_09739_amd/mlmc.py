@@ -16,9 +16,10 @@ LIB_PATH = os.path.join(HERE, "libmlmc.so")
 MLMC_OK, MLMC_EINVAL, MLMC_ENOMEM, MLMC_ENODEV, MLMC_EHIP, MLMC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MLMC_FP64, MLMC_FP32, MLMC_FP16 = 0, 1, 2
 MLMC_BF16 = 3   # emulated bfloat16 (dyadic approximations only)
-MLMC_RV_EXACT, MLMC_RV_PWL16, MLMC_RV_CUBIC16, MLMC_RV_MLP = 0, 1, 2, 3
+MLMC_RV_EXACT, MLMC_RV_PWL16, MLMC_RV_CUBIC16, MLMC_RV_MLP, MLMC_RV_PCONST4096 = 0, 1, 2, 3, 4
 MLMC_EXACT, MLMC_APPROX_PWL16, MLMC_APPROX_CUBIC16, MLMC_APPROX_MLP = 0, 1, 2, 3
 MLMC_NESTED_PWL16, MLMC_NESTED_CUBIC16, MLMC_NESTED_MLP = 5, 6, 7
+MLMC_APPROX_PCONST4096, MLMC_NESTED_PCONST4096 = 4, 8
 MLMC_TERM_TWO_WAY, MLMC_TERM_FOUR_WAY, MLMC_TERM_TWO_WAY_EXACT, MLMC_TERM_ROUNDING = 0, 1, 2, 3
 MLMC_PAYOFF_X, MLMC_PAYOFF_CALL = 0, 1
 MLMC_SCHEME_EM, MLMC_SCHEME_MILSTEIN = 0, 1
@@ -82,6 +83,7 @@ _SIGNATURES = {
                                      ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, _P, _P]),
     "mlmc_icdf": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _P, _P]),
     "mlmc_table": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "mlmc_pconst_table": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "mlmc_last_error": (ctypes.c_char_p, []),
     "mlmc_batch_create": (ctypes.c_int, [ctypes.POINTER(mlmc_item_t), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(mlmc_batch_cfg_t), _P, ctypes.POINTER(_P)]),
@@ -215,6 +217,13 @@ def mlmc_table(rv, precision):
     buf = (ctypes.c_double * 64)()
     _check(lib().mlmc_table(rv, precision, buf))
     return [[buf[4 * j + i] for i in range(4)] for j in range(16)]
+
+
+def mlmc_pconst_table(precision):
+    """The 2048 lower-half cell means of MLMC_RV_PCONST4096 (rounded to precision, widened)."""
+    buf = (ctypes.c_double * 2048)()
+    _check(lib().mlmc_pconst_table(precision, buf))
+    return list(buf)
 
 
 def item(sde, level, n_paths, precision, kahan=0, seed=0, *, pset=0, stream=1):

@@ -44,7 +44,7 @@ def _gpu_visible():
 @pytest.mark.parametrize("kw,code", [
     (dict(level=-1), M.MLMC_EINVAL), (dict(level=25), M.MLMC_EINVAL), (dict(precision=4), M.MLMC_EINVAL),
     (dict(precision=M.MLMC_BF16), M.MLMC_EINVAL), (dict(precision=M.MLMC_BF16, rv_mode=M.MLMC_NESTED_MLP), M.MLMC_EINVAL),
-    (dict(rv_mode=4), M.MLMC_EINVAL), (dict(rv_mode=8), M.MLMC_EINVAL), (dict(kahan=2), M.MLMC_EINVAL),
+    (dict(rv_mode=-1), M.MLMC_EINVAL), (dict(rv_mode=9), M.MLMC_EINVAL), (dict(kahan=2), M.MLMC_EINVAL),
     (dict(precision=M.MLMC_FP32, rv_mode=M.MLMC_EXACT), M.MLMC_EINVAL), (dict(n_paths=2 ** 32 + 1), M.MLMC_EINVAL)])
 def test_invalid_arguments(kw, code):
     a = dict(level=3, n_paths=10, precision=M.MLMC_FP64, rv_mode=M.MLMC_EXACT, kahan=0)
@@ -111,6 +111,15 @@ def test_library_table_matches_oracle_table(rv, deg):
         np.testing.assert_array_equal(np.array(M.mlmc_table(rv, p))[:, :deg + 1], want.astype(dt).astype(np.float64))
     # bfloat16: one rounding of the binary64 coefficients to 8 significant bits
     np.testing.assert_array_equal(np.array(M.mlmc_table(rv, M.MLMC_BF16))[:, :deg + 1], fp.round_bits(want, 8))
+
+
+def test_library_pconst_table_matches_oracle():
+    want = np.array(tables.pconst())
+    got = np.array(M.mlmc_pconst_table(M.MLMC_FP64))
+    assert got.shape == (2048,)
+    assert np.max(np.abs(got - want) / np.abs(want)) < 1e-15
+    for p, prec in ((M.MLMC_FP32, fp.FP32), (M.MLMC_FP16, fp.FP16), (M.MLMC_BF16, fp.BF16)):
+        np.testing.assert_array_equal(np.array(M.mlmc_pconst_table(p)), fp.to64(fp.rn(prec, want)))
 
 
 def test_batch_validation_before_device():

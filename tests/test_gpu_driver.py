@@ -46,3 +46,13 @@ def test_milstein_adaptive_mixture_is_unbiased():
     assert abs(out["estimate"] - exact) <= 4.0 * out["std_error"], (out["estimate"], exact, out["std_error"])
     assert out["std_error"] <= eps / math.sqrt(2) * 1.25
     assert out["predicted_seconds"] <= min(out["predicted_seconds_single_option"].values()) * (1 + 1e-12)
+
+
+def test_mixture_with_table_lookup_options_is_unbiased():
+    eps = 1e-4
+    out = D.adaptive_mlmc(M.gbm(), eps, options=D.TABLE_OPTIONS, n_pilot=1 << 16, seed=17)
+    L = out["L"]
+    exact = (1.0 + 0.05 * 2.0 ** -L) ** (2 ** L)
+    assert abs(out["estimate"] - exact) <= 4.0 * out["std_error"], (out["estimate"], exact, out["std_error"])
+    assert out["std_error"] <= eps / math.sqrt(2) * 1.25
+    assert set(out["predicted_seconds_single_option"]) == {o.name for o in D.TABLE_OPTIONS}
