@@ -168,9 +168,9 @@ int mlmc_level_run(const mlmc_level_args_t* args, mlmc_result_t* out);
 /* Asynchronous level call on hip_stream.  args: host.  d_out: device, 8 doubles
  * (sum[0..3], sumsq[0..3]) written when the stream reaches the call.  d_workspace:
  * device scratch of at least mlmc_level_workspace_bytes(args) bytes (8-byte aligned; it
- * holds the chunk partial sums and the stage rows and ticket counter of the fixed-order
- * two-stage reduction, which the call initialises itself), or NULL to use the library's
- * per-device scratch (calls that overlap on one device then race). */
+ * holds the chunk partial sums and the stage rows of the fixed-order two-stage reduction,
+ * all written by the call before they are read), or NULL to use the library's per-device
+ * scratch (calls that overlap on one device then race). */
 int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspace,
                   size_t workspace_bytes, void* hip_stream);
 

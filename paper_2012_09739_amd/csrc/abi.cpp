@@ -367,17 +367,16 @@ int enqueue_level(DevState& st, const mlmc_level_args_t* a, const Variant& v, do
     p.out_pc_bar = out_pc_bar;
     p.out_xf_tilde = out_xf_tilde;
     hipError_t e;
-    // layout of the workspace: chunk partials, stage rows, ticket counter
+    // layout of the workspace: chunk partials, then the stage rows
     double* stage = partials + (n_chunks == 0 ? 1 : n_chunks) * kPartial;
-    uint32_t* counter = (uint32_t*)(stage + kStageRowsMax * kPartial);
-    p.reduce_counter = d_out ? counter : nullptr;
-    // launched also for no chunks: the level kernel arms the reduction's counter
     int grid, block;
     launch_shape(st, n_chunks, &grid, &block);
-    e = launch_level(v, p, grid, block, s);
-    if (e != hipSuccess) return hip_fail(e, "level kernel launch");
-    if (d_out) {
-        e = launch_reduce(partials, n_chunks, stage, counter, d_out, s);
+    if (n_chunks > 0) {
+        e = launch_level(v, p, grid, block, s);
+        if (e != hipSuccess) return hip_fail(e, "level kernel launch");
+    }
+    if (d_out) {  // with no chunks the first stage reads no row and the sums are zero
+        e = launch_reduce(partials, n_chunks, stage, d_out, s);
         if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
     }
     return MLMC_OK;

@@ -41,7 +41,6 @@ struct mlmc_batch {
     uint32_t* d_counter = nullptr;
     unsigned long long* d_ticks = nullptr;  // per item: wall-clock ticks summed over its tasks
     double* d_stage = nullptr;               // per item: stage rows of the two-stage reduction
-    uint32_t* d_item_counter = nullptr;      // per item: ticket counter of that reduction
     uint2* d_reduce_blocks = nullptr;        // (item, stage block) of every reduction block
     uint32_t n_reduce_blocks = 0;
     uint64_t n_tasks = 0;
@@ -65,13 +64,10 @@ __host__ __device__ inline int variant_of(int precision, int kahan) {
 
 // Clears the queue counter and the per-item tick sums (a kernel, not a memset, so that the
 // captured graph holds no memset node).
-__global__ void batch_reset(uint32_t* counter, unsigned long long* ticks, uint32_t* item_counter, uint32_t n_items) {
+__global__ void batch_reset(uint32_t* counter, unsigned long long* ticks, uint32_t n_items) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) counter[0] = 0u;
-    for (uint32_t k = i; k < n_items; k += gridDim.x * blockDim.x) {
-        ticks[k] = 0ull;
-        item_counter[k] = 0u;
-    }
+    for (uint32_t k = i; k < n_items; k += gridDim.x * blockDim.x) ticks[k] = 0ull;
 }
 
 template <int RV>
@@ -122,19 +118,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void b
     }
 }
 
-// Per item the same two-stage fixed-order reduction as a single-level call.  Block k is
-// stage block blocks[k].y of item blocks[k].x; an item's stage rows sit at the start of its
-// own range of partial-row slots in `stage` (it has at most as many stage rows as rows).
-__global__ __launch_bounds__(kReduceBlock) void batch_reduce(const double* __restrict__ partials,
-                                                             const uint64_t* __restrict__ row_off,
-                                                             const uint64_t* __restrict__ rows,
-                                                             const uint2* __restrict__ blocks, double* stage,
-                                                             uint32_t* item_counter, double* __restrict__ out) {
+// Per item the same two-stage fixed-order reduction as a single-level call.  First stage:
+// block k is stage block blocks[k].y of item blocks[k].x; an item's stage rows sit at the
+// start of its own range of partial-row slots in `stage` (it has at most as many stage rows
+// as rows).  Second stage: block i sums the stage rows of item i.
+__global__ __launch_bounds__(kReduceBlock) void batch_reduce_stage1(const double* __restrict__ partials,
+                                                                    const uint64_t* __restrict__ row_off,
+                                                                    const uint64_t* __restrict__ rows,
+                                                                    const uint2* __restrict__ blocks,
+                                                                    double* __restrict__ stage) {
     __shared__ double s[kPartial][kReduceBlock];
     const uint2 bl = blocks[blockIdx.x];
     const uint32_t item = bl.x;
-    reduce_two_stage(partials + row_off[item] * kPartial, rows[item], stage + row_off[item] * kPartial,
-                     item_counter + item, out + (uint64_t)item * kPartial, bl.y, s);
+    reduce_stage1(partials + row_off[item] * kPartial, rows[item], stage + row_off[item] * kPartial, bl.y, s);
+}
+
+__global__ __launch_bounds__(kReduceBlock) void batch_reduce_stage2(const uint64_t* __restrict__ row_off,
+                                                                    const uint64_t* __restrict__ rows,
+                                                                    const double* __restrict__ stage,
+                                                                    double* __restrict__ out) {
+    __shared__ double s[kPartial][kReduceBlock];
+    const uint32_t item = blockIdx.x;
+    reduce_stage2(stage + row_off[item] * kPartial, rows[item], out + (uint64_t)item * kPartial, s);
 }
 
 constexpr mlmc_batch_cfg_t kDefaultCfg = {16, 1024, 12, 0};
@@ -228,7 +233,7 @@ int enqueue(mlmc_batch* b, hipStream_t s) {
     const int blocks = std::max(1, b->n_cu * b->cfg.waves_per_cu / 4);
     const uint32_t n_items = (uint32_t)b->items.size();
     hipLaunchKernelGGL(batch_reset, dim3(std::min<uint32_t>(64, (n_items + 255) / 256)), dim3(256), 0, s, b->d_counter,
-                       b->d_ticks, b->d_item_counter, n_items);
+                       b->d_ticks, n_items);
     int rc = hipck(hipGetLastError(), "queue reset launch");
     if (rc) return rc;
     if (b->rv == MLMC_RV_CUBIC16)
@@ -241,8 +246,12 @@ int enqueue(mlmc_batch* b, hipStream_t s) {
                            (const __half*)b->tab16, b->exact_tab, b->d_ticks);
     rc = hipck(hipGetLastError(), "batch kernel launch");
     if (rc) return rc;
-    hipLaunchKernelGGL(batch_reduce, dim3(b->n_reduce_blocks), dim3(kReduceBlock), 0, s, b->d_partials, b->d_row_off,
-                       b->d_rows, b->d_reduce_blocks, b->d_stage, b->d_item_counter, b->d_out);
+    hipLaunchKernelGGL(batch_reduce_stage1, dim3(b->n_reduce_blocks), dim3(kReduceBlock), 0, s, b->d_partials,
+                       b->d_row_off, b->d_rows, b->d_reduce_blocks, b->d_stage);
+    rc = hipck(hipGetLastError(), "batch reduction launch");
+    if (rc) return rc;
+    hipLaunchKernelGGL(batch_reduce_stage2, dim3(n_items), dim3(kReduceBlock), 0, s, b->d_row_off, b->d_rows,
+                       b->d_stage, b->d_out);
     return hipck(hipGetLastError(), "batch reduction launch");
 }
 
@@ -291,7 +300,7 @@ void free_plan(mlmc_batch* b) {
     drop_graph(b);
     for (void* p : {(void*)b->d_params, (void*)b->d_variant, (void*)b->d_row_off, (void*)b->d_rows,
                     (void*)b->d_partials, (void*)b->d_tasks, (void*)b->d_counter, (void*)b->d_ticks,
-                    (void*)b->d_stage, (void*)b->d_item_counter, (void*)b->d_reduce_blocks})
+                    (void*)b->d_stage, (void*)b->d_reduce_blocks})
         if (p) (void)hipFree(p);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
@@ -371,7 +380,6 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
     alloc((void**)&b->d_counter, sizeof(uint32_t) * 64, "hipMalloc counter");
     alloc((void**)&b->d_ticks, sizeof(unsigned long long) * n_items, "hipMalloc item ticks");
     alloc((void**)&b->d_stage, sizeof(double) * kPartial * total_rows, "hipMalloc stage rows");
-    alloc((void**)&b->d_item_counter, sizeof(uint32_t) * n_items, "hipMalloc item counters");
     if (!rc) rc = hipck(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
     if (rc) {
         free_plan(b);

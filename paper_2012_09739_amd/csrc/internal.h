@@ -41,7 +41,6 @@ struct LevelParams {
     const void* mlp;       // MLP inference image (rv = MLP)
     const void* exact_tab; // ExactTable: log cells and piecewise coefficients (exact inverse CDF)
     double* partials;      // [n_chunks][kPartial] chunk partial sums
-    uint32_t* reduce_counter;  // ticket counter of the two-stage reduction (zeroed here), or null
     // optional per-path outputs (device, n_paths entries each, may be null)
     double* out_pf_hat;
     double* out_pc_hat;
@@ -62,11 +61,10 @@ struct Variant {
 
 // Launch helpers implemented in the .hip translation units.
 hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
-hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* stage, uint32_t* counter,
-                         double* d_out, hipStream_t s);
+hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* stage, double* d_out, hipStream_t s);
 
-// Workspace of one level call: the chunk partials, the stage rows of the two-stage
-// reduction (at most 128 rows of kPartial doubles) and its ticket counter.
+// Workspace of one level call: the chunk partials and the stage rows of the two-stage
+// reduction (at most 128 rows of kPartial doubles), plus 64 bytes of slack.
 constexpr uint64_t kStageRowsMax = 128;
 inline size_t level_workspace_bytes(uint64_t n_chunks) {
     return (size_t)((n_chunks == 0 ? 1 : n_chunks) + kStageRowsMax) * kPartial * sizeof(double) + 64;

@@ -11,15 +11,20 @@ namespace mlmc {
 
 namespace {
 
-// Sums n_chunks rows of 8 chunk partials in a fixed order: thread t accumulates rows
-// t, t + 256, ... sequentially, then a fixed tree over the 256 threads.  The order depends
-// only on n_chunks, so results do not depend on the level kernel's launch shape, and the
-// batched sweep (one block per item) reproduces the single-level sums bit for bit.
-__global__ __launch_bounds__(kReduceBlock) void reduce_chunks(const double* __restrict__ partials, uint64_t n_chunks,
-                                                              double* stage, uint32_t* counter,
-                                                              double* __restrict__ out) {
+// The two stages of the fixed-order reduction of n_chunks rows of 8 chunk partials (the
+// tree of reduce_stage1 / reduce_stage2).  The order depends only on n_chunks, so results do
+// not depend on the level kernel's launch shape, and the batched sweep, which runs the same
+// stages per item, reproduces the single-level sums bit for bit.
+__global__ __launch_bounds__(kReduceBlock) void reduce_chunks_stage1(const double* __restrict__ partials,
+                                                                     uint64_t n_chunks, double* __restrict__ stage) {
     __shared__ double s[kPartial][kReduceBlock];
-    reduce_two_stage(partials, n_chunks, stage, counter, out, blockIdx.x, s);
+    reduce_stage1(partials, n_chunks, stage, blockIdx.x, s);
+}
+
+__global__ __launch_bounds__(kReduceBlock) void reduce_chunks_stage2(const double* __restrict__ stage,
+                                                                     uint64_t n_chunks, double* __restrict__ out) {
+    __shared__ double s[kPartial][kReduceBlock];
+    reduce_stage2(stage, n_chunks, out, s);
 }
 
 __global__ void uniforms_kernel(uint32_t k0, uint32_t k1, uint32_t ctr2, uint32_t pset, uint64_t path0,
@@ -77,10 +82,12 @@ int grid_for(uint64_t n, int block) {
 
 }  // namespace
 
-hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* stage, uint32_t* counter,
-                         double* d_out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_chunks, dim3(stage_blocks(n_chunks)), dim3(kReduceBlock), 0, s, partials, n_chunks,
-                       stage, counter, d_out);
+hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* stage, double* d_out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_chunks_stage1, dim3(stage_blocks(n_chunks)), dim3(kReduceBlock), 0, s, partials, n_chunks,
+                       stage);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_chunks_stage2, dim3(1), dim3(kReduceBlock), 0, s, stage, n_chunks, d_out);
     return hipGetLastError();
 }
 

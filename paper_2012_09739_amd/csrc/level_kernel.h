@@ -361,8 +361,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == ML
     __shared__ double s_tab64[(kDyadic || kPconst) && DIAG ? kTabN : 1];
     __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
     constexpr bool kNeedLog = RV == MLMC_RV_EXACT || NESTED || RV == MLMC_RV_MLP;
-    // arm the ticket counter of the reduction that follows this kernel on the stream
-    if (prm.reduce_counter && blockIdx.x == 0 && threadIdx.x == 0) *prm.reduce_counter = 0u;
     __shared__ __align__(16) unsigned char s_ex_raw[kNeedLog ? sizeof(ExactTable) : 16];
     const ExactTable* s_ex = (const ExactTable*)s_ex_raw;
     if constexpr (kNeedLog) {

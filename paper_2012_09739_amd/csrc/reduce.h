@@ -48,35 +48,31 @@ __device__ __forceinline__ void reduce_rows_block(const double* __restrict__ row
     if (threadIdx.x < kPartial) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
-// Two-stage fixed-order reduction of n chunk rows by one kernel of R = stage_blocks(n)
-// blocks.  Block b sums rows [b per, min(n, (b + 1) per)), per = ceil(n / R), with
-// reduce_rows_block into stage row b; the block that finishes last (a device-scope fence
-// before a ticket taken from *counter) sums the R stage rows in order into out and
-// re-arms the counter.  The tree depends on n only, never on the launch or the timing, so
-// every caller with the same rows gets the same bits.  *counter must be 0 on entry.
+// Two-stage fixed-order reduction of n chunk rows.  Stage 1 runs R = stage_blocks(n) blocks:
+// block b sums rows [b per, min(n, (b + 1) per)), per = ceil(n / R), with reduce_rows_block
+// into stage row b.  Stage 2 (one block) sums the R stage rows in order.  The tree depends on
+// n only, never on the launch or the timing, so every caller with the same rows gets the same
+// bits.  The stages are separate kernels: the kernel boundary publishes the stage rows to the
+// second stage, where a device-scope fence inside one kernel would have every block write
+// back its XCD's L2.
 constexpr uint32_t kStageBlocks = (uint32_t)kStageRowsMax;
 __host__ __device__ inline uint32_t stage_blocks(uint64_t n) {
     const uint64_t r = (n + 63) / 64;
     return r < 1 ? 1u : (r > kStageBlocks ? kStageBlocks : (uint32_t)r);
 }
 
-__device__ __forceinline__ void reduce_two_stage(const double* __restrict__ rows, uint64_t n, double* stage,
-                                                 uint32_t* counter, double* __restrict__ out, uint32_t b,
-                                                 double (*s)[kReduceBlock]) {
+__device__ __forceinline__ void reduce_stage1(const double* __restrict__ rows, uint64_t n, double* __restrict__ stage,
+                                              uint32_t b, double (*s)[kReduceBlock]) {
     const uint32_t R = stage_blocks(n);
     const uint64_t per = (n + R - 1) / R;
     const uint64_t lo = (uint64_t)b * per < n ? (uint64_t)b * per : n;
     const uint64_t hi = lo + per < n ? lo + per : n;
     reduce_rows_block(rows + lo * kPartial, hi - lo, stage + (uint64_t)b * kPartial, s);
-    __threadfence();  // this block's stage row is visible device-wide before its ticket
-    __shared__ uint32_t ticket;
-    __syncthreads();
-    if (threadIdx.x == 0) ticket = atomicAdd(counter, 1u);
-    __syncthreads();
-    if (ticket != R - 1) return;
-    __threadfence();  // every other stage row is visible to this, the last, block
-    reduce_rows_block(stage, R, out, s);
-    if (threadIdx.x == 0) *counter = 0u;
+}
+
+__device__ __forceinline__ void reduce_stage2(const double* __restrict__ stage, uint64_t n, double* __restrict__ out,
+                                              double (*s)[kReduceBlock]) {
+    reduce_rows_block(stage, stage_blocks(n), out, s);
 }
 
 }  // namespace mlmc

@@ -86,7 +86,7 @@ def test_null_pointers_rejected():
 
 
 def test_workspace_size():
-    # chunk partials (8 doubles per chunk), 128 stage rows of the reduction, its counter
+    # chunk partials (8 doubles per chunk), 128 stage rows of the reduction, 64 bytes of slack
     args = M.level_args(M.gbm(), 5, 1000, M.MLMC_FP32, M.MLMC_NESTED_PWL16)
     assert M.mlmc_level_workspace_bytes(args) == (16 + 128) * 8 * 8 + 64     # 16 chunks of 64 paths
     args16 = M.level_args(M.gbm(), 5, 1000, M.MLMC_FP16, M.MLMC_NESTED_PWL16)
