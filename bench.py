@@ -50,8 +50,8 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 ALG_OPS_PER_STEP = 59.0
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (90.0 * 2.0 + 1024.03125) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "556e085af83b6151ee161e645b4294959df42d92970033831b81eb07e108f414"
+TRAFFIC_BYTES_PER_LAUNCH = (89.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "3168cad18a8c9e485e5d8913fea7a70800106c4099873a08962dc4bb35e932e7"
 KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
                   "icdf_exact_coeffs.h")
 
