@@ -13,7 +13,11 @@ rounding per operation:
   the precision experiments around Figure 3) has no NumPy dtype: values are held in float64
   arrays of class ``BF16Array``, whose + - x max min round every result to 8 significant
   bits (``round_bits``), the correctly rounded result since the float64 operation on two
-  8-bit operands is exact or at least 2*8+2 bits wide.
+  8-bit operands is exact or at least 2*8+2 bits wide;
+* P17, a 16-bit-mantissa format (17 significant bits; the fourth width of the same
+  precision experiments, between binary16 and binary32), likewise in ``P17Array``: float64
+  has 53 >= 2*17+2 bits, so rounding its result again to 17 bits is the correctly rounded
+  17-bit result.  Neither emulation models subnormals or overflow (the paths stay near 1).
 
 Nothing here uses fused multiply-add: the method's operations are the separate roundings
 the paper writes.
@@ -21,10 +25,11 @@ the paper writes.
 
 import numpy as np
 
-FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+FP64, FP32, FP16, BF16, P17 = 0, 1, 2, 3, 4
 DTYPES = {FP64: np.float64, FP32: np.float32, FP16: np.float16}
 # unit roundoff of each format (half the gap between 1 and the next representable number)
-UNIT_ROUNDOFF = {FP64: 2.0 ** -53, FP32: 2.0 ** -24, FP16: 2.0 ** -11, BF16: 2.0 ** -8}
+UNIT_ROUNDOFF = {FP64: 2.0 ** -53, FP32: 2.0 ** -24, FP16: 2.0 ** -11, BF16: 2.0 ** -8, P17: 2.0 ** -17}
+SIGNIFICAND_BITS = {FP64: 53, FP32: 24, FP16: 11, BF16: 8, P17: 17}
 
 
 def round_bits(x, p):
@@ -41,17 +46,32 @@ def round_bits(x, p):
     return r.view(np.float64)
 
 
-class BF16Array(np.ndarray):
-    """bfloat16 values held in float64: the listed ufuncs round their result to 8 bits."""
+class RoundedArray(np.ndarray):
+    """Values of a P-bit format held in float64: the listed ufuncs round their result to P
+    significant bits (subclasses fix P)."""
 
+    P = 53
     _ROUNDED = (np.add, np.subtract, np.multiply, np.maximum, np.minimum, np.negative, np.absolute)
 
     def __array_ufunc__(self, ufunc, method, *inputs, **kwargs):
         args = [a.view(np.ndarray) if isinstance(a, np.ndarray) else a for a in inputs]
         res = getattr(ufunc, method)(*args, **kwargs)
         if method == "__call__" and ufunc in self._ROUNDED:
-            return round_bits(res, 8).view(BF16Array)
+            return round_bits(res, self.P).view(type(self))
         return res
+
+
+class BF16Array(RoundedArray):
+    """bfloat16 values held in float64 (8 significant bits)."""
+    P = 8
+
+
+class P17Array(RoundedArray):
+    """16-bit-mantissa values held in float64 (17 significant bits)."""
+    P = 17
+
+
+_EMULATED = {BF16: BF16Array, P17: P17Array}
 
 
 def bf16(x):
@@ -59,29 +79,36 @@ def bf16(x):
     return round_bits(x, 8).view(BF16Array)
 
 
+def p17(x):
+    """R_17(x) of float64 value(s) as a P17Array (one correctly rounded conversion)."""
+    return round_bits(x, 17).view(P17Array)
+
+
 def dtype(precision):
-    """The constructor of values of precision p (a NumPy scalar type, or bf16)."""
-    return bf16 if precision == BF16 else DTYPES[precision]
+    """The constructor of values of precision p (a NumPy scalar type, or an emulated format)."""
+    if precision in _EMULATED:
+        return bf16 if precision == BF16 else p17
+    return DTYPES[precision]
 
 
 def rn(precision, x):
     """R_p(x): round float64 value(s) x to precision p (one correctly rounded conversion)."""
-    if precision == BF16:
-        return bf16(x)
+    if precision in _EMULATED:
+        return dtype(precision)(x)
     return np.asarray(x, dtype=np.float64).astype(DTYPES[precision])
 
 
 def full(value, n):
     """n copies of a value of some precision, in that precision."""
-    if isinstance(value, BF16Array):
-        return np.full(n, float(value)).view(BF16Array)
+    if isinstance(value, RoundedArray):
+        return np.full(n, float(value)).view(type(value))
     return np.full(n, value, dtype=np.asarray(value).dtype)
 
 
 def like(ref, values):
     """values (exactly representable in ref's precision) converted to ref's precision."""
-    if isinstance(ref, BF16Array):
-        return np.asarray(values, dtype=np.float64).view(BF16Array)
+    if isinstance(ref, RoundedArray):
+        return np.asarray(values, dtype=np.float64).view(type(ref))
     return np.asarray(values).astype(np.asarray(ref).dtype)
 
 

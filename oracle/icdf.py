@@ -21,8 +21,8 @@ Word-to-interval map (the build's reading of the dyadic construction; u = (x + 1
     t  = (x' + 1/2) 2^(k+1-32) - 1   if k <= 15      (u' = 2^-(k+1) (1 + t))
          (x' + 1/2) 2^-16           otherwise        (u' = 2^-16 t)
     Z~ = s ? -q_j(t) : q_j(t)
-The local coordinate is exact in float64; precision p uses R_p(t), except binary16 which
-uses R_16(R_32(t)) (the coordinate is formed in binary32 and then narrowed).
+The local coordinate is exact in float64; precision p uses R_p(t), except binary16 and
+bfloat16, which use R_p(R_32(t)) (the coordinate is formed in binary32 and then narrowed).
 
 ``approx`` with RV_PCONST: the piecewise-constant variable of ``oracle.tables.pconst`` on
 2^b equal cells (b = 12): with s and x' as above, cell i = x' >> (32 - b) of the lower half
