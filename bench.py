@@ -44,14 +44,15 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 #   exact inverse CDF: 26 binary64 operations (x, y = 1 - x^2, table log with a
 #     degree-3 log1p, interval and coordinate of g, degree-7 piece, x g) + 4
 #     32-bit ones x 1/2                                                            28.0
-#   binary64 fine and half coarse EM update: 5 + 6/2                               8.0
+#   binary64 fine and half coarse EM update, products fused into the sum:
+#     fine cb X, ca X, fma, add = 4; coarse Z sum + 4 = 5, half of it            6.5
 #   piecewise-linear inverse CDF, binary32: 13 32-bit operations x 1/2             6.5
 #   binary32 fine and half coarse Kahan EM update: (8 + 9/2) x 1/2                 6.25
-ALG_OPS_PER_STEP = 59.0
+ALG_OPS_PER_STEP = 57.5
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (89.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "3168cad18a8c9e485e5d8913fea7a70800106c4099873a08962dc4bb35e932e7"
+TRAFFIC_BYTES_PER_LAUNCH = (89.0 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "9cd6c0ed3a7304665416745c3bd12d24d45d27ed6eab0587ffcd3553f56cdbe8"
 KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
                   "icdf_exact_coeffs.h")
 

@@ -40,17 +40,27 @@ struct RoundBF16 {
     __device__ __forceinline__ float operator()(float x) const { return round_bf16(x); }
 };
 
-// The increment dX of one step: A (+) B, and for Milstein (A (+) B) (+) M.
+// The increment dX of one step: A (+) B, and for Milstein (A (+) B) (+) M.  The low-precision
+// paths round every operation as the method states.  The binary64 paths (the exact pair and
+// the diagnostic's reference) stand for exact arithmetic: there the products that feed an
+// addition are fused, dX = fma(cb X, Z, ca X) (and M by fma(Z, Z, -k)), two roundings fewer
+// per step, far below every tolerance these paths are compared with.
 template <int SCHEME, typename T, typename R>
 __device__ __forceinline__ T increment(T X, T z, T ca, T cb, T cm, T k, R r) {
-    const T A = r(ca * X);
-    const T B = r(r(cb * X) * z);
-    const T dX = r(A + B);
-    if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) {
-        const T M = r(r(cm * X) * r(r(z * z) - k));
-        return r(dX + M);
+    if constexpr (sizeof(T) == 8) {
+        const double dX = __builtin_fma(cb * X, z, ca * X);
+        if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) return __builtin_fma(cm * X, __builtin_fma(z, z, -k), dX);
+        else return dX;
     } else {
-        return dX;
+        const T A = r(ca * X);
+        const T B = r(r(cb * X) * z);
+        const T dX = r(A + B);
+        if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) {
+            const T M = r(r(cm * X) * r(r(z * z) - k));
+            return r(dX + M);
+        } else {
+            return dX;
+        }
     }
 }
 
@@ -345,7 +355,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
 // SHORT: the instance for levels with fewer than 4 fine steps (exact variables one word at a time).
 // SCHEME: MLMC_SCHEME_EM or MLMC_SCHEME_MILSTEIN.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == MLMC_FP32 || PREC == MLMC_FP64) && RV != MLMC_RV_MLP ? 7 : 1))) void level_kernel(const LevelParams prm) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == MLMC_FP32 || PREC == MLMC_FP64) && RV != MLMC_RV_MLP && !SHORT ? 7 : 1))) void level_kernel(const LevelParams prm) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
     constexpr bool kPconst = (RV == MLMC_RV_PCONST4096);
