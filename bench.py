@@ -318,7 +318,7 @@ def reports(M, E, torch):
     rep["batch_64psets_levels0to14"] = {
         "items": len(items), "tasks": n_tasks, "ms_per_sweep": ms, "path_steps": steps,
         "path_steps_per_s": steps / ms * 1e3,
-        "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level],
+        "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level],
         "wave_slot_utilisation": sum(wave_s) / (resident * ms * 1e-3),
         "cost_per_sample_s_by_level": [float(np.mean(per_level[l])) for l in sorted(per_level)]}
 

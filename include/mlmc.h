@@ -235,7 +235,10 @@ typedef struct {
     int32_t task_steps;      /* fine steps per task at level 0 (tasks of level l hold      */
                              /* max(1, task_steps >> l) chunks): 1..2^20                 */
     int32_t priority_level;  /* tasks of level >= this run at raised wave priority; 25=off */
-    int32_t reserved;
+    int32_t coop_level;      /* binary32 items of level >= this (2..25; 25 = off) run each   */
+                             /* chunk on a whole 4-wave block: three waves draw the       */
+                             /* variables of the next 12 steps into LDS while one wave    */
+                             /* advances the paths (same operations, same bits)           */
 } mlmc_batch_cfg_t;
 
 typedef struct mlmc_batch mlmc_batch_t; /* opaque plan (device task list + captured graph) */

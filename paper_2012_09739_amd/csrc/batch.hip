@@ -7,8 +7,16 @@
 // wavefront pops tasks from a device counter until the queue is empty, so every wave
 // reaches the exit.  Tasks at or above a chosen level run at raised wave priority, which
 // keeps the long dependent chains issuing while short tasks share the SIMD.  A chunk
-// writes its 8 partial sums to a per-item row; one block per item then reduces its rows
-// in the same fixed order as the single-level path (reduce_rows_block).
+// writes its 8 partial sums to a per-item row; the rows of every item are then reduced in
+// the same fixed order as the single-level path.
+//
+// Cooperative chunks: the chunks of the deepest binary32 items (level >= coop_level) are
+// serial chains of up to 2^24 steps, and one wavefront alone runs them latency bound.  Each
+// block first pops such chunks from a block queue and runs one chunk with all four waves:
+// three producer waves draw the uniforms and both inverse CDFs for the next phase of 12
+// steps into an LDS ring while the consumer wave advances the four coupled paths through
+// the current phase, one barrier per phase.  The consumer performs exactly the operations
+// of the single-wave code in the same order, so every sum keeps its bits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +46,10 @@ struct mlmc_batch {
     uint64_t* d_rows = nullptr;
     double* d_partials = nullptr;
     uint4* d_tasks = nullptr;
-    uint32_t* d_counter = nullptr;
+    uint2* d_coop = nullptr;                 // cooperative chunks (item, chunk), longest first
+    uint64_t n_coop = 0;
+    uint64_t coop_capacity = 0;
+    uint32_t* d_counter = nullptr;           // [0] wave queue, [1] cooperative block queue
     unsigned long long* d_ticks = nullptr;  // per item: wall-clock ticks summed over its tasks
     double* d_stage = nullptr;               // per item: stage rows of the two-stage reduction
     uint2* d_reduce_blocks = nullptr;        // (item, stage block) of every reduction block
@@ -66,13 +77,122 @@ __host__ __device__ inline int variant_of(int precision, int kahan) {
 // captured graph holds no memset node).
 __global__ void batch_reset(uint32_t* counter, unsigned long long* ticks, uint32_t n_items) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) counter[0] = 0u;
+    if (i == 0) {
+        counter[0] = 0u;
+        counter[1] = 0u;
+    }
     for (uint32_t k = i; k < n_items; k += gridDim.x * blockDim.x) ticks[k] = 0ull;
 }
 
+constexpr int kBatchBlock = 256;
+constexpr int kCoopProducers = kBatchBlock / kWave - 1;  // waves 1..3 of a block
+constexpr int kCoopSteps = 4 * kCoopProducers;            // fine steps per phase: one Philox call per producer
+
+// One cooperative chunk of a nested binary32 item (n_steps >= 4, a multiple of 4) run by
+// the whole block.  Phase f covers fine steps [12 f, 12 f + 12): producer wave p draws
+// Philox call 3 f + p - 1 and writes its four exact (binary64) and approximate (binary32)
+// variables into ring slot f & 1; the consumer, wave 0, reads slot f & 1 while the
+// producers fill slot (f + 1) & 1, and a barrier closes every phase (the same number of
+// barriers in every wave).  The consumer's updates and payoff terms are those of run_chunk
+// for this variant, in the same order.
+template <int RV, bool KAHAN>
+__device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const float* s_tab, const ExactTable* s_ex,
+                               double (*ring_x)[kCoopSteps][kWave], float (*ring_b)[kCoopSteps][kWave]) {
+    constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t local = chunk * kWave + lane;
+    const bool valid = local < prm.n_paths;
+    const uint32_t path = (uint32_t)(prm.path_offset + (valid ? local : 0));
+    const uint32_t n_calls = prm.n_steps / 4;
+    const uint32_t n_phases = (n_calls + kCoopProducers - 1) / kCoopProducers;
+
+    if (wave != 0) {
+        const ExactConsts kc = exact_consts();
+        const uint32_t base = 4 * (wave - 1);
+        for (uint32_t f = 0; f <= n_phases; ++f) {
+            const uint32_t q = f * kCoopProducers + (wave - 1);
+            if (f < n_phases && q < n_calls) {
+                const Words4 r = philox4x32_10(q, path, prm.ctr2, prm.pset, prm.key0, prm.key1);
+                double zx[4];
+                icdf_exact_f64x4(r.w, zx, s_ex, kc);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    ring_x[f & 1][base + i][lane] = zx[i];
+                    ring_b[f & 1][base + i][lane] = approx_rv<RV, DEG, float, MLMC_FP32>(r.w[i], s_tab, nullptr, s_ex->log);
+                }
+            }
+            __syncthreads();  // phase f written; the consumer is done with slot (f + 1) & 1
+        }
+        return;
+    }
+
+    double Xfh = prm.x0_f64, Xch = prm.x0_f64, zh_prev = 0.0;
+    float Xfb = prm.x0_f32, Xcb = Xfb, cfb = 0.0f, ccb = 0.0f, zb_prev = 0.0f;
+    const NoRound rnd{};
+    __syncthreads();  // phase 0 written
+    for (uint32_t f = 0; f < n_phases; ++f) {
+        const uint32_t left = prm.n_steps - f * kCoopSteps;
+        const uint32_t cnt = left < (uint32_t)kCoopSteps ? left : (uint32_t)kCoopSteps;
+#pragma unroll
+        for (int i = 0; i < kCoopSteps; ++i) {
+            if ((uint32_t)i >= cnt) break;
+            const bool coarse = (i & 1) != 0;  // phases start at an even step
+            const double z = ring_x[f & 1][i][lane];
+            em_step<MLMC_SCHEME_EM, double>(Xfh, z, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
+            if (coarse) em_step<MLMC_SCHEME_EM, double>(Xch, zh_prev + z, prm.cac_f64, prm.cb_f64, prm.cm_f64, 2.0);
+            else zh_prev = z;
+            const float zb = ring_b[f & 1][i][lane];
+            if constexpr (KAHAN) {
+                em_step_kahan<MLMC_SCHEME_EM, float>(Xfb, cfb, zb, prm.ca_f32, prm.cb_f32, prm.cm_f32, 1.0f, rnd);
+                if (coarse)
+                    em_step_kahan<MLMC_SCHEME_EM, float>(Xcb, ccb, rnd(zb_prev + zb), prm.cac_f32, prm.cb_f32, prm.cm_f32,
+                                                         2.0f, rnd);
+            } else {
+                em_step<MLMC_SCHEME_EM, float>(Xfb, zb, prm.ca_f32, prm.cb_f32, prm.cm_f32, 1.0f, rnd);
+                if (coarse) em_step<MLMC_SCHEME_EM, float>(Xcb, rnd(zb_prev + zb), prm.cac_f32, prm.cb_f32, prm.cm_f32, 2.0f, rnd);
+            }
+            if (!coarse) zb_prev = zb;
+        }
+        __syncthreads();  // phase f + 1 written; slot f & 1 free again
+    }
+
+    // payoffs and differences (binary64), as run_chunk for a nested binary32 chunk
+    double acc[kPartial];
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
+    const bool has_coarse = prm.level >= 1;
+    double t[kTerms] = {0.0, 0.0, 0.0, 0.0};
+    const double pfh = payoff<double>(Xfh, prm.k_f64, prm.payoff);
+    const double pch = has_coarse ? payoff<double>(Xch, prm.k_f64, prm.payoff) : 0.0;
+    const float kk = prm.k_f32;
+    const double pfb = (double)payoff<float>(Xfb, kk, prm.payoff, rnd);
+    const double pcb = has_coarse ? (double)payoff<float>(Xcb, kk, prm.payoff, rnd) : 0.0;
+    t[MLMC_TERM_TWO_WAY] = pfb - pcb;
+    t[MLMC_TERM_TWO_WAY_EXACT] = pfh - pch;
+    t[MLMC_TERM_FOUR_WAY] = t[MLMC_TERM_TWO_WAY_EXACT] - t[MLMC_TERM_TWO_WAY];
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < kTerms; ++k) {
+            acc[k] += t[k];
+            acc[kTerms + k] += t[k] * t[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPartial; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane < kPartial) {
+        double v = acc[0];
+#pragma unroll
+        for (int k = 1; k < kPartial; ++k)
+            if (lane == (uint32_t)k) v = acc[k];
+        prm.partials[chunk * kPartial + lane] = v;
+    }
+}
+
 template <int RV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
+__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(5))) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
                                                     const uint4* __restrict__ tasks, uint32_t n_tasks,
+                                                    const uint2* __restrict__ coop, uint32_t n_coop,
                                                     uint32_t* __restrict__ counter, const float* __restrict__ tab32,
                                                     const __half* __restrict__ tab16, const void* __restrict__ exact_tab,
                                                     unsigned long long* __restrict__ ticks) {
@@ -80,6 +200,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void b
     __shared__ float s_tab32[kTableRows * 4];
     __shared__ __half s_tab16[kTableRows * 4];
     __shared__ __align__(16) unsigned char s_ex_raw[sizeof(ExactTable)];
+    __shared__ double ring_x[2][kCoopSteps][kWave];
+    __shared__ float ring_b[2][kCoopSteps][kWave];
+    __shared__ uint32_t s_pop;
     const ExactTable* s_ex = (const ExactTable*)s_ex_raw;
     for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
         s_tab32[i] = prescaled_coeff(tab32[i], i % (DEG + 1));
@@ -88,6 +211,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void b
     stage_exact_table(s_ex_raw, exact_tab);
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
+    // cooperative chunks first: the block pops one, all four waves run it (block-uniform loop)
+    for (;;) {
+        if (threadIdx.x == 0) s_pop = atomicAdd(&counter[1], 1u);
+        __syncthreads();
+        const uint32_t c = s_pop;
+        __syncthreads();  // every thread has read s_pop before it is written again
+        if (c >= n_coop) break;
+        const uint2 ct = coop[c];
+        const LevelParams& prm = params[ct.x];
+        __builtin_amdgcn_s_setprio(3);
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        if (variant[ct.x] & 1) run_chunk_coop<RV, true>(prm, ct.y, s_tab32, s_ex, ring_x, ring_b);
+        else run_chunk_coop<RV, false>(prm, ct.y, s_tab32, s_ex, ring_x, ring_b);
+        const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+        if (lane == 0) atomicAdd(&ticks[ct.x], (unsigned long long)(t1 - t0));
+        __builtin_amdgcn_s_setprio(0);
+    }
     for (;;) {
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(counter, 1u);
@@ -142,12 +282,13 @@ __global__ __launch_bounds__(kReduceBlock) void batch_reduce_stage2(const uint64
     reduce_stage2(stage + row_off[item] * kPartial, rows[item], out + (uint64_t)item * kPartial, s);
 }
 
-constexpr mlmc_batch_cfg_t kDefaultCfg = {16, 1024, 12, 0};
+constexpr mlmc_batch_cfg_t kDefaultCfg = {16, 1024, 12, 12};
 
 int validate_cfg(const mlmc_batch_cfg_t& c) {
     if (c.waves_per_cu < 4 || c.waves_per_cu > 32) return set_error(MLMC_EINVAL, "waves_per_cu must be 4..32");
     if (c.task_steps < 1 || c.task_steps > (1 << 20)) return set_error(MLMC_EINVAL, "task_steps must be 1..2^20");
     if (c.priority_level < 0 || c.priority_level > 25) return set_error(MLMC_EINVAL, "priority_level must be 0..25");
+    if (c.coop_level < 2 || c.coop_level > 25) return set_error(MLMC_EINVAL, "coop_level must be 2..25");
     return MLMC_OK;
 }
 
@@ -157,8 +298,14 @@ mlmc_batch_cfg_t merged(const mlmc_batch_cfg_t* c) {
         if (c->waves_per_cu) r.waves_per_cu = c->waves_per_cu;
         if (c->task_steps) r.task_steps = c->task_steps;
         if (c->priority_level) r.priority_level = c->priority_level;
+        if (c->coop_level) r.coop_level = c->coop_level;
     }
     return r;
+}
+
+// whether an item's chunks run cooperatively (binary32, at least coop_level; n_steps >= 4)
+bool is_coop(const mlmc_item_t& it, const mlmc_batch_cfg_t& c) {
+    return it.precision == MLMC_FP32 && it.level >= c.coop_level && it.level >= 2;
 }
 
 std::string signature(const mlmc_batch& b) {
@@ -178,13 +325,16 @@ bool cache_lookup(const std::string& key, mlmc_batch_cfg_t* c) {
     const char* path = std::getenv("MLMC_AUTOTUNE_CACHE");
     if (!path || !*path) return false;
     std::ifstream f(path);
-    std::string k;
-    int a, s, p;
-    while (f >> k >> a >> s >> p)
-        if (k == key) {
-            *c = mlmc_batch_cfg_t{a, s, p, 0};
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string k;
+        int a, s, p, q;
+        if ((in >> k >> a >> s >> p >> q) && k == key) {
+            *c = mlmc_batch_cfg_t{a, s, p, q};
             return validate_cfg(*c) == MLMC_OK;
         }
+    }
     return false;
 }
 
@@ -200,22 +350,28 @@ void cache_store(const std::string& key, const mlmc_batch_cfg_t& c) {
     }
     std::ofstream f(path, std::ios::trunc);
     for (const std::string& l : keep) f << l << "\n";
-    f << key << " " << c.waves_per_cu << " " << c.task_steps << " " << c.priority_level << "\n";
+    f << key << " " << c.waves_per_cu << " " << c.task_steps << " " << c.priority_level << " " << c.coop_level << "\n";
 }
 
 int hipck(hipError_t e, const char* what) {
     return e == hipSuccess ? MLMC_OK : set_error(MLMC_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Task list for the current configuration: ordered by decreasing work.
-std::vector<uint4> build_tasks(const mlmc_batch& b, const std::vector<uint64_t>& rows) {
+// Task list for the current configuration: ordered by decreasing work.  Chunks of
+// cooperative items go to `coop` instead (one entry per chunk, deepest first).
+std::vector<uint4> build_tasks(const mlmc_batch& b, const std::vector<uint64_t>& rows, std::vector<uint2>* coop) {
     struct T {
         uint64_t work;
         uint4 t;
     };
     std::vector<T> ts;
+    std::vector<std::pair<int, uint2>> cs;
     for (size_t i = 0; i < b.items.size(); ++i) {
         const int l = b.items[i].level;
+        if (is_coop(b.items[i], b.cfg)) {
+            for (uint64_t c = 0; c < rows[i]; ++c) cs.push_back({l, make_uint2((uint32_t)i, (uint32_t)c)});
+            continue;
+        }
         const uint64_t per = std::max<uint64_t>(1, (uint64_t)b.cfg.task_steps >> l);
         const uint32_t prio = l >= b.cfg.priority_level ? 1u : 0u;
         for (uint64_t c = 0; c < rows[i]; c += per) {
@@ -224,26 +380,31 @@ std::vector<uint4> build_tasks(const mlmc_batch& b, const std::vector<uint64_t>&
         }
     }
     std::stable_sort(ts.begin(), ts.end(), [](const T& a, const T& c) { return a.work > c.work; });
+    std::stable_sort(cs.begin(), cs.end(), [](const std::pair<int, uint2>& a, const std::pair<int, uint2>& c) {
+        return a.first > c.first;
+    });
+    coop->resize(cs.size());
+    for (size_t i = 0; i < cs.size(); ++i) (*coop)[i] = cs[i].second;
     std::vector<uint4> out(ts.size());
     for (size_t i = 0; i < ts.size(); ++i) out[i] = ts[i].t;
     return out;
 }
 
 int enqueue(mlmc_batch* b, hipStream_t s) {
-    const int blocks = std::max(1, b->n_cu * b->cfg.waves_per_cu / 4);
+    const int blocks = std::max(1, b->n_cu * b->cfg.waves_per_cu / (kBatchBlock / kWave));
     const uint32_t n_items = (uint32_t)b->items.size();
     hipLaunchKernelGGL(batch_reset, dim3(std::min<uint32_t>(64, (n_items + 255) / 256)), dim3(256), 0, s, b->d_counter,
                        b->d_ticks, n_items);
     int rc = hipck(hipGetLastError(), "queue reset launch");
     if (rc) return rc;
     if (b->rv == MLMC_RV_CUBIC16)
-        hipLaunchKernelGGL(batch_kernel<MLMC_RV_CUBIC16>, dim3(blocks), dim3(256), 0, s, b->d_params, b->d_variant,
-                           b->d_tasks, (uint32_t)b->n_tasks, b->d_counter, (const float*)b->tab32,
-                           (const __half*)b->tab16, b->exact_tab, b->d_ticks);
+        hipLaunchKernelGGL(batch_kernel<MLMC_RV_CUBIC16>, dim3(blocks), dim3(kBatchBlock), 0, s, b->d_params,
+                           b->d_variant, b->d_tasks, (uint32_t)b->n_tasks, b->d_coop, (uint32_t)b->n_coop,
+                           b->d_counter, (const float*)b->tab32, (const __half*)b->tab16, b->exact_tab, b->d_ticks);
     else
-        hipLaunchKernelGGL(batch_kernel<MLMC_RV_PWL16>, dim3(blocks), dim3(256), 0, s, b->d_params, b->d_variant,
-                           b->d_tasks, (uint32_t)b->n_tasks, b->d_counter, (const float*)b->tab32,
-                           (const __half*)b->tab16, b->exact_tab, b->d_ticks);
+        hipLaunchKernelGGL(batch_kernel<MLMC_RV_PWL16>, dim3(blocks), dim3(kBatchBlock), 0, s, b->d_params,
+                           b->d_variant, b->d_tasks, (uint32_t)b->n_tasks, b->d_coop, (uint32_t)b->n_coop,
+                           b->d_counter, (const float*)b->tab32, (const __half*)b->tab16, b->exact_tab, b->d_ticks);
     rc = hipck(hipGetLastError(), "batch kernel launch");
     if (rc) return rc;
     hipLaunchKernelGGL(batch_reduce_stage1, dim3(b->n_reduce_blocks), dim3(kReduceBlock), 0, s, b->d_partials,
@@ -269,18 +430,33 @@ int prepare(mlmc_batch* b) {
         const uint64_t cp = chunk_paths(b->items[i].precision);
         rows[i] = (b->items[i].n_paths + cp - 1) / cp;
     }
-    const std::vector<uint4> tasks = build_tasks(*b, rows);
+    std::vector<uint2> coop;
+    const std::vector<uint4> tasks = build_tasks(*b, rows, &coop);
     int rc;
-    if (tasks.size() > b->task_capacity) {
+    if (tasks.size() > b->task_capacity || (b->d_tasks == nullptr && !tasks.empty())) {
         if (b->d_tasks) (void)hipFree(b->d_tasks);
         b->d_tasks = nullptr;
-        if ((rc = hipck(hipMalloc(&b->d_tasks, tasks.size() * sizeof(uint4)), "hipMalloc tasks"))) return rc;
+        if ((rc = hipck(hipMalloc(&b->d_tasks, std::max<size_t>(1, tasks.size()) * sizeof(uint4)), "hipMalloc tasks")))
+            return rc;
         b->task_capacity = tasks.size();
     }
-    if ((rc = hipck(hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(uint4), hipMemcpyHostToDevice),
+    if (!tasks.empty() &&
+        (rc = hipck(hipMemcpy(b->d_tasks, tasks.data(), tasks.size() * sizeof(uint4), hipMemcpyHostToDevice),
                     "hipMemcpy tasks")))
         return rc;
     b->n_tasks = tasks.size();
+    if (coop.size() > b->coop_capacity || (b->d_coop == nullptr && !coop.empty())) {
+        if (b->d_coop) (void)hipFree(b->d_coop);
+        b->d_coop = nullptr;
+        if ((rc = hipck(hipMalloc(&b->d_coop, std::max<size_t>(1, coop.size()) * sizeof(uint2)), "hipMalloc coop")))
+            return rc;
+        b->coop_capacity = coop.size();
+    }
+    if (!coop.empty() &&
+        (rc = hipck(hipMemcpy(b->d_coop, coop.data(), coop.size() * sizeof(uint2), hipMemcpyHostToDevice),
+                    "hipMemcpy coop")))
+        return rc;
+    b->n_coop = coop.size();
     drop_graph(b);
     if ((rc = hipck(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")))
         return rc;
@@ -299,8 +475,8 @@ int prepare(mlmc_batch* b) {
 void free_plan(mlmc_batch* b) {
     drop_graph(b);
     for (void* p : {(void*)b->d_params, (void*)b->d_variant, (void*)b->d_row_off, (void*)b->d_rows,
-                    (void*)b->d_partials, (void*)b->d_tasks, (void*)b->d_counter, (void*)b->d_ticks,
-                    (void*)b->d_stage, (void*)b->d_reduce_blocks})
+                    (void*)b->d_partials, (void*)b->d_tasks, (void*)b->d_coop, (void*)b->d_counter,
+                    (void*)b->d_ticks, (void*)b->d_stage, (void*)b->d_reduce_blocks})
         if (p) (void)hipFree(p);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
@@ -477,14 +653,16 @@ int mlmc_batch_autotune(mlmc_batch_t* plan, int repeats, mlmc_batch_cfg_t* best)
     for (int w = 8; w <= 32; w += 4)
         if (w <= 4 * blocks_per_cu) waves.push_back(w);
     if (waves.empty()) waves.push_back(4 * std::max(1, blocks_per_cu));
-    const int steps[] = {64, 128, 256, 1024};
-    const int prios[] = {10, 12, 25};
+    const int steps[] = {64, 256, 1024};
+    const int prios[] = {12, 25};
+    const int coops[] = {11, 12, 13, 25};
     mlmc_batch_cfg_t winner = plan->cfg;
     float best_ms = 1e30f;
     for (int w : waves)
         for (int st : steps)
-            for (int pr : prios) {
-                plan->cfg = mlmc_batch_cfg_t{w, st, pr, 0};
+            for (int pr : prios)
+                for (int co : coops) {
+                plan->cfg = mlmc_batch_cfg_t{w, st, pr, co};
                 if ((rc = prepare(plan))) goto done;
                 if ((rc = hipck(hipGraphLaunch(plan->exec, plan->cap_stream), "warm-up replay"))) goto done;
                 if ((rc = hipck(hipEventRecord(e0, plan->cap_stream), "hipEventRecord"))) goto done;

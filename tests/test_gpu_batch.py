@@ -1,7 +1,8 @@
 """GPU tests of the batched persistent sweep: every item equals the single-level call bit for
-bit (same kernels' chunk partials, same fixed-order reduction), graph replays equal the eager
-launch, the oracle agrees on small items, the autotuner keeps results unchanged, and the
-full 64-parameter-set x 15-level sweep runs."""
+bit (same kernels' chunk partials, same fixed-order reduction), also when its chunks run
+cooperatively on whole blocks, graph replays equal the eager launch, the oracle agrees on
+small items, the autotuner keeps results unchanged, and the full 64-parameter-set x
+15-level sweep runs."""
 
 import math
 
@@ -58,6 +59,29 @@ def test_batch_items_equal_single_level_calls(rv):
         got = out.cpu().numpy()
         for i, it in enumerate(items):
             np.testing.assert_array_equal(got[i], single_level(it, rv), err_msg=str(meta[i][:4]))
+    finally:
+        M.mlmc_batch_destroy(plan)
+
+
+@pytest.mark.parametrize("kahan32", [0, 1])
+@pytest.mark.parametrize("coop_level", [2, 7])
+def test_cooperative_chunks_equal_single_level_calls(coop_level, kahan32):
+    # binary32 items from level 2 (one Philox call: a partial first phase) to 12 (1024 calls:
+    # 342 phases, the last one partial), path counts not multiples of the chunk
+    torch = torch_cuda()
+    psets = W.batch_parameter_sets(2, seed=9)
+    items, meta = make_items(psets, range(13), lambda l: max(70, 9000 >> l) + 5, split=1, kahan32=kahan32)
+    out = torch.zeros((len(items), 8), dtype=torch.float64, device="cuda")
+    cfg = M.mlmc_batch_cfg_t(16, 256, 25, coop_level)
+    plan = M.mlmc_batch_create(items, M.MLMC_RV_PWL16, out, cfg)
+    try:
+        M.mlmc_batch_run(plan)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        info, _ = M.mlmc_batch_info(plan)
+        assert info.coop_level == coop_level
+        for i, it in enumerate(items):
+            np.testing.assert_array_equal(got[i], single_level(it, M.MLMC_RV_PWL16), err_msg=str(meta[i][:4]))
     finally:
         M.mlmc_batch_destroy(plan)
 
@@ -119,8 +143,8 @@ def test_autotune_keeps_results_and_returns_valid_shape(tmp_path, monkeypatch):
         best = M.mlmc_batch_autotune(plan, 1)
         assert 4 <= best.waves_per_cu <= 32 and best.task_steps >= 1
         cfg, n_tasks = M.mlmc_batch_info(plan)
-        assert (cfg.waves_per_cu, cfg.task_steps, cfg.priority_level) == (best.waves_per_cu, best.task_steps,
-                                                                           best.priority_level)
+        assert (cfg.waves_per_cu, cfg.task_steps, cfg.priority_level, cfg.coop_level) == (
+            best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level)
         assert n_tasks > 0
         out.zero_()
         M.mlmc_batch_run(plan)
@@ -133,8 +157,8 @@ def test_autotune_keeps_results_and_returns_valid_shape(tmp_path, monkeypatch):
     plan2 = M.mlmc_batch_create(items, M.MLMC_RV_PWL16, out)
     try:
         cfg2, _ = M.mlmc_batch_info(plan2)
-        assert (cfg2.waves_per_cu, cfg2.task_steps, cfg2.priority_level) == (best.waves_per_cu, best.task_steps,
-                                                                             best.priority_level)
+        assert (cfg2.waves_per_cu, cfg2.task_steps, cfg2.priority_level, cfg2.coop_level) == (
+            best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level)
     finally:
         M.mlmc_batch_destroy(plan2)
 
