@@ -190,7 +190,7 @@ __device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const flo
 }
 
 template <int RV>
-__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(5))) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
+__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
                                                     const uint4* __restrict__ tasks, uint32_t n_tasks,
                                                     const uint2* __restrict__ coop, uint32_t n_coop,
                                                     uint32_t* __restrict__ counter, const float* __restrict__ tab32,
