@@ -5,8 +5,8 @@
 //
 // Exact (binary64): Phi^{-1}(u) = x g(w) with x = 2u - 1 and w = -log((1 - x)(1 + x)),
 // g an entire function of w.  -log is table driven (256 cells) and g is piecewise: on each
-// of 86 intervals of width 1/4 covering every w of a 32-bit word, one polynomial of
-// degree 7 in the local coordinate, its coefficients read per lane from the same table (in
+// of 344 intervals of width 1/16 covering every w of a 32-bit word, one polynomial of
+// degree 5 in the local coordinate, its coefficients read per lane from the same table (in
 // LDS or global memory), so every lane runs the same instructions whatever its interval.
 // x is exact and y = 1 - x^2 = (1 - x)(1 + x) is rounded once (one fma); the result is
 // exactly odd under word -> 2^32 - 1 - word.
@@ -65,11 +65,11 @@ __device__ __forceinline__ double sgpr_const(double c) {
 }
 
 // Table of the exact variable: the log cells and, interval-major, the piecewise
-// coefficients of g (piece[k][j] is coefficient j of interval k: one 64-byte row per
-// interval, read with four 16-byte loads from one address).
+// coefficients of g (piece[k][j] is coefficient j of interval k: one 48-byte row per
+// interval, read with three 16-byte loads from one address).
 constexpr int kPieces = MLMC_ICDF_PIECES;
 constexpr int kPieceDeg = MLMC_ICDF_PIECE_DEG;
-static_assert(kPieceDeg == 7, "one 64-byte row of 8 coefficients per interval");
+static_assert((kPieceDeg + 1) % 2 == 0, "rows of whole 16-byte pairs of coefficients");
 struct ExactTable {
     LogCell log[kLogCells];
     double piece[kPieces][kPieceDeg + 1];
@@ -85,7 +85,7 @@ __device__ __forceinline__ double icdf_y(double x) {
     return __builtin_fma(-x, x, 1.0);
 }
 
-// g(w): interval k = floor(4 |w|) and local coordinate f = 4 |w| - k, both exact.  w is
+// g(w): interval k = floor(16 |w|) and local coordinate f = 16 |w| - k, both exact.  w is
 // below 0 only by a rounding when y rounds to 1 (|x| < 2^-26.5), where g(|w|) = g(0) to
 // far below binary64 resolution; the absolute value is a free source modifier.
 __device__ __forceinline__ double icdf_g(double w, const double (*__restrict__ piece)[kPieceDeg + 1]) {
