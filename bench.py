@@ -44,15 +44,15 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 #   exact inverse CDF: 24 binary64 operations (x, y = 1 - x^2, table log with a
 #     degree-3 log1p, interval and coordinate of g, degree-5 piece, x g) + 4
 #     32-bit ones x 1/2                                                            26.0
-#   binary64 fine and half coarse EM update, products fused into the sum:
-#     fine cb X, ca X, fma, add = 4; coarse Z sum + 4 = 5, half of it            6.5
+#   binary64 fine and half coarse EM update in the product form of GBM,
+#     X = fma(X, fma(cb, Z, ca), X): fine 2; coarse Z sum + 2 = 3, half of it      3.5
 #   piecewise-linear inverse CDF, binary32: 13 32-bit operations x 1/2             6.5
 #   binary32 fine and half coarse Kahan EM update: (8 + 9/2) x 1/2                 6.25
-ALG_OPS_PER_STEP = 55.5
+ALG_OPS_PER_STEP = 52.5
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (134.0 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "a173334a67aa248eb650f5020cddc4f0ba2aab0af8217f378fac1f632e1e1419"
+TRAFFIC_BYTES_PER_LAUNCH = (129.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "139bdf37887252ba353f718c799a788b86bfc4a8ef1a163dd09f83c3aa73a6b3"
 KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
                   "icdf_exact_coeffs.h")
 

@@ -40,33 +40,37 @@ struct RoundBF16 {
     __device__ __forceinline__ float operator()(float x) const { return round_bf16(x); }
 };
 
-// The increment dX of one step: A (+) B, and for Milstein (A (+) B) (+) M.  The low-precision
-// paths round every operation as the method states.  The binary64 paths (the exact pair and
-// the diagnostic's reference) stand for exact arithmetic: there the products that feed an
-// addition are fused, dX = fma(cb X, Z, ca X) (and M by fma(Z, Z, -k)), two roundings fewer
-// per step, far below every tolerance these paths are compared with.
+// The increment dX of one step in a low-precision path: A (+) B, and for Milstein
+// (A (+) B) (+) M, every operation rounded as the method states.
 template <int SCHEME, typename T, typename R>
 __device__ __forceinline__ T increment(T X, T z, T ca, T cb, T cm, T k, R r) {
-    if constexpr (sizeof(T) == 8) {
-        const double dX = __builtin_fma(cb * X, z, ca * X);
-        if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) return __builtin_fma(cm * X, __builtin_fma(z, z, -k), dX);
-        else return dX;
+    const T A = r(ca * X);
+    const T B = r(r(cb * X) * z);
+    const T dX = r(A + B);
+    if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) {
+        const T M = r(r(cm * X) * r(r(z * z) - k));
+        return r(dX + M);
     } else {
-        const T A = r(ca * X);
-        const T B = r(r(cb * X) * z);
-        const T dX = r(A + B);
-        if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) {
-            const T M = r(r(cm * X) * r(r(z * z) - k));
-            return r(dX + M);
-        } else {
-            return dX;
-        }
+        return dX;
     }
 }
 
+// One state update.  The binary64 paths (the exact pair, the binary64 approximate pair and
+// the diagnostic's reference) stand for exact arithmetic; for GBM the drift and diffusion
+// are linear in X, so there X + ca X + cb X Z = X (1 + d) with d = ca + cb Z (Milstein:
+// + cm (Z^2 - k)) is evaluated as fma(X, d, X), d by fmas that do not depend on X: two
+// roundings per step instead of four, a one-instruction dependent chain, and an error far
+// below every tolerance these paths are compared with.  The low-precision paths keep the
+// separately rounded X (+) dX.
 template <int SCHEME, typename T, typename R = NoRound>
 __device__ __forceinline__ void em_step(T& X, T z, T ca, T cb, T cm, T k, R r = R{}) {
-    X = r(X + increment<SCHEME>(X, z, ca, cb, cm, k, r));
+    if constexpr (sizeof(T) == 8) {
+        double d = __builtin_fma(cb, z, ca);
+        if constexpr (SCHEME == MLMC_SCHEME_MILSTEIN) d = __builtin_fma(cm, __builtin_fma(z, z, -k), d);
+        X = __builtin_fma(X, d, X);
+    } else {
+        X = r(X + increment<SCHEME>(X, z, ca, cb, cm, k, r));
+    }
 }
 
 template <int SCHEME, typename T, typename R = NoRound>
@@ -206,6 +210,10 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
 
     ExactConsts kc{};
     if constexpr (kNeedExact) kc = exact_consts();
+    // the binary64 addends ca, cac of d = fma(cb, Z, ca) held in VGPRs for the chunk: an fma
+    // reads at most one scalar operand, and cb is the other constant
+    double ca64 = prm.ca_f64, cac64 = prm.cac_f64;
+    asm volatile("" : "+v"(ca64), "+v"(cac64));
     for (uint32_t q = 0; q < n_calls; ++q) {
         Words4 r[L];
 #pragma unroll
@@ -232,9 +240,9 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     const double z = zx[l][i];
-                    em_step<SCHEME, double>(Xfh[l], z, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
+                    em_step<SCHEME, double>(Xfh[l], z, ca64, prm.cb_f64, prm.cm_f64, 1.0);
                     if (coarse)
-                        em_step<SCHEME, double>(Xch[l], zh_prev[l] + z, prm.cac_f64, prm.cb_f64, prm.cm_f64, 2.0);
+                        em_step<SCHEME, double>(Xch[l], zh_prev[l] + z, cac64, prm.cb_f64, prm.cm_f64, 2.0);
                     else zh_prev[l] = z;
                 }
             }
@@ -278,7 +286,7 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
                     if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw, s_ex->log);
                     else if constexpr (RV == MLMC_RV_PCONST4096) zt = icdf_pconst_f64(r[l].w[i], s_tab64);
                     else zt = icdf_dyadic_f64<DEG>(r[l].w[i], s_tab64);
-                    em_step<SCHEME, double>(Xft[l], zt, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
+                    em_step<SCHEME, double>(Xft[l], zt, ca64, prm.cb_f64, prm.cm_f64, 1.0);
                 }
             }
         }
