@@ -229,3 +229,37 @@ def test_invalid_arguments_rejected_on_gpu():
     with pytest.raises(M.MlmcError) as e:
         M.mlmc_level(M.gbm(T=-1.0), 3, 10, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, 0)
     assert e.value.code == M.MLMC_EINVAL
+
+
+def test_maximum_path_count_level0():
+    """2^32 paths (the largest n_paths) at level 0: the sums are finite, the exact two-way mean
+    is E[X_1] = 1 + mu within the central-limit bound, the four-way mean is 0 within its
+    bound, and the two halves (path_offset 0 and 2^31) add up to the whole within rounding."""
+    sde = M.gbm()
+    whole = M.mlmc_level_run(M.level_args(sde, 0, 1 << 32, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, 17))
+    lo = M.mlmc_level_run(M.level_args(sde, 0, 1 << 31, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, 17))
+    hi = M.mlmc_level_run(M.level_args(sde, 0, 1 << 31, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, 17,
+                                       path_offset=1 << 31))
+    m = float(1 << 32)
+    assert all(math.isfinite(v) for v in whole["sum"][:3] + whole["sumsq"][:3])
+    mean_e, var_e = M.mean_var(whole["sum"][2], whole["sumsq"][2], m)
+    assert abs(mean_e - 1.05) < 5 * math.sqrt(var_e / m)
+    assert abs(var_e / 0.04 - 1) < 1e-3
+    mean_4, var_4 = M.mean_var(whole["sum"][1], whole["sumsq"][1], m)
+    assert abs(mean_4) < 5 * math.sqrt(var_4 / m)
+    for k in range(3):
+        assert abs(lo["sum"][k] + hi["sum"][k] - whole["sum"][k]) <= 1e-12 * abs(whole["sumsq"][k]) ** 0.5 * m ** 0.5
+        assert abs(lo["sumsq"][k] + hi["sumsq"][k] - whole["sumsq"][k]) <= 1e-12 * whole["sumsq"][k]
+
+
+def test_full_size_sampled_paths_milstein_fp32():
+    n, level = W.NESTED_FP32["n_paths"], 10
+    sde = W.NESTED_FP32["sde"]
+    g = gpu_paths(sde, level, n, M.MLMC_FP32, M.MLMC_RV_PWL16, True, 1, 0, scheme=M.MLMC_SCHEME_MILSTEIN)
+    idx = W.sampled_paths(n, 48)
+    o = mlmc.level_paths(level, idx, sde, rv_mode=mlmc.RV_PWL, precision=fp.FP32, nested=True, kahan=True,
+                         seed=0, stream=1, scheme=mlmc.SCHEME_MILSTEIN)
+    assert np.all(close(g["pf_hat"][idx], o["Pf_hat"], 1e-13))
+    assert np.all(close(g["pc_hat"][idx], o["Pc_hat"], 1e-13))
+    assert np.all(close(g["pf_bar"][idx], o["Pf_bar"], 1e-5))
+    assert np.all(close(g["pc_bar"][idx], o["Pc_bar"], 1e-5))
