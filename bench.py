@@ -73,6 +73,9 @@ def traffic_bytes():
     return TRAFFIC_BYTES_PER_LAUNCH
 
 
+REPORT_LEGS = ("plain", "fp16", "batch", "mlp", "sweep", "adaptive", "milstein", "pconst")
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -81,7 +84,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-speedup", action="store_true", help="skip the equal-variance legs")
     p.add_argument("--no-reports", action="store_true",
-                   help="skip the report legs of the other workloads (fp64 plain, fp16, batch, mlp)")
+                   help="skip the report legs of the other workloads (fp64 plain, fp16, batch, mlp, ...)")
+    p.add_argument("--reports", default=",".join(REPORT_LEGS),
+                   help="comma-separated report legs to run: " + ", ".join(REPORT_LEGS))
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a device copy of known size (HBM counter calibration)")
     return p.parse_args()
@@ -155,7 +160,12 @@ def main():
         extra["copy_calibration_bytes"] = 2 * src.numel() * 4
 
     if not a.no_reports:
-        extra["reports"] = reports(M, E, torch)
+        legs = tuple(x for x in a.reports.split(",") if x)
+        unknown = [x for x in legs if x not in REPORT_LEGS]
+        if unknown:
+            print("unknown report legs: %s" % ", ".join(unknown), file=sys.stderr)
+            sys.exit(2)
+        extra["reports"] = reports(M, E, torch, legs)
 
     line = {
         "metric": "coupled path-steps/s FP16/FP32 vs FP64 at equal MLMC variance; % VALU peak",
@@ -235,8 +245,8 @@ def _level_costs(M, sde, levels, n, prec, mode, kahan, seed=SEED):
     return rows
 
 
-def reports(M, E, torch):
-    """Report legs of the other workloads (not timed into `value`)."""
+def reports(M, E, torch, legs=REPORT_LEGS):
+    """Report legs of the other workloads (not timed into `value`); `legs` selects them."""
     import numpy as np
 
     import mlmc_workloads as W
@@ -246,193 +256,202 @@ def reports(M, E, torch):
     cost = lambda rows: [r["cost_seconds"] / r["n_paths"] for r in rows]  # noqa: E731
     rate = lambda rows: sum(r["path_steps"] for r in rows) / sum(r["cost_seconds"] for r in rows)  # noqa: E731
 
-    # plain MLMC in binary64, exact inverse CDF: GBM, P = X_T, levels 0..5, 10^4 paths, seed 0
-    c1 = W.PLAIN_FP64
-    rows = _level_costs(M, M.gbm(), c1["levels"], c1["n_paths"], M.MLMC_FP64, M.MLMC_EXACT, 0)
-    rep["plain_fp64_levels0to5_1e4"] = {"mean": mean(rows, 0), "var": var(rows, 0),
-                                        "theta_hat": E.plain_estimate([(r["sum"][0], r["n_paths"]) for r in rows]),
-                                        "theta_limit_e^mu": math.exp(0.05), "path_steps_per_s": rate(rows)}
-
-    # packed binary16 with Kahan, piecewise cubic, binary64 exact branch: levels 0..6, 2^24 paths
-    c3 = W.NESTED_FP16
-    call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
-    nested16 = []
-    for l in c3["levels"]:
-        args = M.level_args(call, l, c3["n_paths"], M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1, SEED, diag=1)
-        out = torch.zeros(8, dtype=torch.float64, device="cuda")
-        M.mlmc_level_ex(args, out)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        M.mlmc_level_ex(args, out)
-        e1.record()
-        torch.cuda.synchronize()
-        o = out.cpu().numpy()
-        nested16.append({"sum": list(o[:4]), "sumsq": list(o[4:]), "n_paths": c3["n_paths"],
-                         "path_steps": c3["n_paths"] << l, "cost_seconds": e0.elapsed_time(e1) * 1e-3})
-    plain = _level_costs(M, call, c3["levels"], c3["n_paths"], M.MLMC_FP64, M.MLMC_EXACT, 0)
-    approx16 = _level_costs(M, call, c3["levels"], c3["n_paths"], M.MLMC_FP16, M.MLMC_APPROX_CUBIC16, 1)
-    rho = 2.0 ** -11
-    bound = [2 ** l * rho ** 2 * (1 + 0.05 * 2.0 ** -l) ** (2 * 2 ** l) * math.exp(0.04) * math.exp(0.14)
-             for l in c3["levels"]]
-    rep["nested_fp16_cubic16_kahan_levels0to6_2p24"] = {
-        "nested_path_steps_per_s": rate(nested16), "approx_two_way_path_steps_per_s": rate(approx16),
-        "plain_fp64_path_steps_per_s": rate(plain),
-        "rounding_variance": var(nested16, 3), "rounding_variance_bound_B_l": bound,
-        "four_way_var": var(nested16, 1), "two_way_exact_var": var(nested16, 2),
-        "speedup_T_hat_over_T_bar": E.speedup_equal_variance(var(plain, 0), cost(plain), var(approx16, 0),
-                                                             cost(approx16), var(nested16, 1), cost(nested16))}
-
-    # batched ragged sweep: 64 GBM parameter sets x levels 0..14, fp16 (l <= 6) / fp32 (l > 6)
-    psets = W.batch_parameter_sets(W.BATCH_PSETS, seed=0)
-    items = []
-    for p, d in enumerate(psets):
-        g = M.gbm(mu=d["mu"], sigma=d["sigma"])
-        for l in W.BATCH_LEVELS:
-            prec = M.MLMC_FP16 if l <= 6 else M.MLMC_FP32
-            items.append(M.item(g, l, W.batch_paths(l), prec, 1 if prec == M.MLMC_FP16 else 0, SEED, pset=p))
-    out = torch.zeros((len(items), 8), dtype=torch.float64, device="cuda")
-    plan = M.mlmc_batch_create(items, M.MLMC_RV_PWL16, out)
-    try:
-        best = M.mlmc_batch_autotune(plan, 2)
-        M.mlmc_batch_run(plan)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            M.mlmc_batch_run(plan)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / 5
-        cfg, n_tasks = M.mlmc_batch_info(plan)
-        wave_s = M.mlmc_batch_item_times(plan, len(items))
-    finally:
-        M.mlmc_batch_destroy(plan)
-    steps = sum(it.n_paths << it.level for it in items)
-    resident = cfg.waves_per_cu * torch.cuda.get_device_properties(0).multi_processor_count
-    # device time attributed to items in proportion to their wavefront time; cost per sample
-    share = [w / sum(wave_s) * ms * 1e-3 for w in wave_s]
-    per_level = {}
-    for it, c in zip(items, share):
-        per_level.setdefault(it.level, []).append(c / it.n_paths)
-    rep["batch_64psets_levels0to14"] = {
-        "items": len(items), "tasks": n_tasks, "ms_per_sweep": ms, "path_steps": steps,
-        "path_steps_per_s": steps / ms * 1e3,
-        "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level],
-        "wave_slot_utilisation": sum(wave_s) / (resident * ms * 1e-3),
-        "cost_per_sample_s_by_level": [float(np.mean(per_level[l])) for l in sorted(per_level)]}
-
-    # learned inverse CDF: train on 2^20 pairs, nested four-way levels 0..10 at 2^22 paths vs PWL16
-    params = torch.tensor(W.mlp_initial_params(0), dtype=torch.float32, device="cuda")
-    t0 = time.perf_counter()
-    hist = M.mlmc_mlp_train(M.mlp_cfg(n_pairs=W.MLP_TRAIN_PAIRS), params)
-    train_s = time.perf_counter() - t0
-    M.mlmc_mlp_load(params)
-    words = torch.arange(2 ** 20, dtype=torch.int64, device="cuda").mul(4096).add(2047).to(torch.int32)
-    zs = {}
-    for rv in (M.MLMC_RV_EXACT, M.MLMC_RV_MLP, M.MLMC_RV_PWL16):
-        z = torch.empty(2 ** 20, dtype=torch.float64, device="cuda")
-        M.mlmc_icdf(words, 2 ** 20, rv, M.MLMC_FP32, z)
-        zs[rv] = z
-    torch.cuda.synchronize()
-    mlp_rows = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_NESTED_MLP, 0)
-    pwl_rows = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0)
-    rep["mlp_nested_fp32_levels0to10_2p22"] = {
-        "train_seconds": train_s, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
-        "mse_Z_minus_Ztilde": {"mlp": float(((zs[M.MLMC_RV_MLP] - zs[M.MLMC_RV_EXACT]) ** 2).mean()),
-                               "pwl16": float(((zs[M.MLMC_RV_PWL16] - zs[M.MLMC_RV_EXACT]) ** 2).mean())},
-        "four_way_var": {"mlp": var(mlp_rows, 1), "pwl16": var(pwl_rows, 1)},
-        "nested_path_steps_per_s": {"mlp": rate(mlp_rows), "pwl16": rate(pwl_rows)}}
-    # precision-width sweep (Figure 3's question): variance of the rounding difference
-    # X-_N - X~_N against the level for bfloat16 (8 bits), binary16 (11) and binary32 (24),
-    # without and with Kahan, piecewise cubic, payoff X_T, 2^18 paths per level
-    sweep = {}
-    gbm_x = M.gbm()
-    for name, prec in (("bf16", M.MLMC_BF16), ("fp16", M.MLMC_FP16), ("fp32", M.MLMC_FP32)):
-        for k in (0, 1):
-            v = []
-            for l in range(2, 11):
-                args = M.level_args(gbm_x, l, 2 ** 18, prec, M.MLMC_APPROX_CUBIC16, k, SEED, diag=1)
-                o = torch.zeros(8, dtype=torch.float64, device="cuda")
-                M.mlmc_level_ex(args, o)
-                torch.cuda.synchronize()
-                t = o.cpu().numpy()
-                v.append(E.level_stats(t[3], t[7], 2 ** 18)[1])
-            sweep["%s%s" % (name, "_kahan" if k else "")] = v
-    rho = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "fp32": 2.0 ** -24}
-    sweep["levels"] = list(range(2, 11))
-    sweep["bound_B_l"] = {n: [2 ** l * r * r * (1 + 0.05 * 2.0 ** -l) ** (2 * 2 ** l) * math.exp(0.04 + 0.14)
-                              for l in range(2, 11)] for n, r in rho.items()}
-    rep["rounding_variance_precision_sweep_cubic_2p18"] = sweep
-
-    # adaptive MLMC with a per-level precision map from measured costs, against the plain
-    # binary64 estimator at the same accuracy (call payoff, eps = 1e-5)
     from paper_2012_09739_amd import driver as D
-    mixed = D.adaptive_mlmc(call, 1e-5, seed=21)
-    plain = D.adaptive_mlmc(call, 1e-5, options=(D.PLAIN_FP64,), seed=21)
-    with_pc = D.adaptive_mlmc(call, 1e-5, options=D.TABLE_OPTIONS, seed=21)
-    rep["adaptive_mlmc_call_eps1e-5_with_pconst"] = {
-        "estimate": with_pc["estimate"], "std_error": with_pc["std_error"], "L": with_pc["L"],
-        "choice": with_pc["choice"],
-        "predicted_speedup_vs_fp64": with_pc["predicted_seconds_single_option"]["fp64"] / with_pc["predicted_seconds"],
-        "measured_device_seconds": with_pc["measured_seconds"]}
-    rep["adaptive_mlmc_call_eps1e-5"] = {
-        "estimate": mixed["estimate"], "std_error": mixed["std_error"], "L": mixed["L"],
-        "choice": mixed["choice"], "predicted_speedup_vs_fp64": mixed["predicted_seconds_single_option"]["fp64"]
-        / mixed["predicted_seconds"],
-        "measured_device_seconds": mixed["measured_seconds"],
-        "plain_fp64_estimate": plain["estimate"], "plain_fp64_std_error": plain["std_error"],
-        "plain_fp64_measured_device_seconds": plain["measured_seconds"],
-        "measured_speedup_vs_fp64": plain["measured_seconds"] / mixed["measured_seconds"]}
+    call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
+    adaptive_plain = None
+    if "plain" in legs:
+        # plain MLMC in binary64, exact inverse CDF: GBM, P = X_T, levels 0..5, 10^4 paths, seed 0
+        c1 = W.PLAIN_FP64
+        rows = _level_costs(M, M.gbm(), c1["levels"], c1["n_paths"], M.MLMC_FP64, M.MLMC_EXACT, 0)
+        rep["plain_fp64_levels0to5_1e4"] = {"mean": mean(rows, 0), "var": var(rows, 0),
+                                            "theta_hat": E.plain_estimate([(r["sum"][0], r["n_paths"]) for r in rows]),
+                                            "theta_limit_e^mu": math.exp(0.05), "path_steps_per_s": rate(rows)}
 
-    # Milstein (Section 4: order-1 strong convergence moves the work to the coarse levels):
-    # plain binary64 level variances against Euler-Maruyama's, nested rates, and the adaptive
-    # precision map at the same accuracy
-    mil = {}
-    lv = list(range(0, 11))
-    for tag, sch in (("em", M.MLMC_SCHEME_EM), ("milstein", M.MLMC_SCHEME_MILSTEIN)):
-        rows = [M.mlmc_level_run(M.level_args(call, l, 2 ** 20, M.MLMC_FP64, M.MLMC_EXACT, 0, SEED, scheme=sch))
-                for l in lv]
-        mil["plain_fp64_var_" + tag] = var(rows, 0)
-    for tag, prec, mode, k in (("nested_fp32_pwl", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0),
-                               ("nested_fp16_cubic_kahan", M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1),
-                               ("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0)):
-        a = M.level_args(call, 10, 2 ** 20, prec, mode, k, SEED, scheme=M.MLMC_SCHEME_MILSTEIN)
-        M.mlmc_level_run(a)
-        r = M.mlmc_level_run(a)
-        mil["level10_path_steps_per_s_" + tag] = r["path_steps"] / r["cost_seconds"]
-    mil["levels"] = lv
-    m_mixed = D.adaptive_mlmc(call, 1e-5, seed=23, scheme=M.MLMC_SCHEME_MILSTEIN)
-    m_plain = D.adaptive_mlmc(call, 1e-5, options=(D.PLAIN_FP64,), seed=23, scheme=M.MLMC_SCHEME_MILSTEIN)
-    mil["adaptive_call_eps1e-5"] = {
-        "estimate": m_mixed["estimate"], "std_error": m_mixed["std_error"], "L": m_mixed["L"],
-        "choice": m_mixed["choice"],
-        "predicted_speedup_vs_fp64": m_mixed["predicted_seconds_single_option"]["fp64"]
-        / m_mixed["predicted_seconds"],
-        "measured_device_seconds": m_mixed["measured_seconds"],
-        "plain_fp64_estimate": m_plain["estimate"], "plain_fp64_measured_device_seconds": m_plain["measured_seconds"],
-        "measured_speedup_vs_fp64": m_plain["measured_seconds"] / m_mixed["measured_seconds"],
-        "em_plain_fp64_measured_device_seconds": plain["measured_seconds"]}
-    rep["milstein_call"] = mil
+    if "fp16" in legs:
+        # packed binary16 with Kahan, piecewise cubic, binary64 exact branch: levels 0..6, 2^24 paths
+        c3 = W.NESTED_FP16
+        nested16 = []
+        for l in c3["levels"]:
+            args = M.level_args(call, l, c3["n_paths"], M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1, SEED, diag=1)
+            out = torch.zeros(8, dtype=torch.float64, device="cuda")
+            M.mlmc_level_ex(args, out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            M.mlmc_level_ex(args, out)
+            e1.record()
+            torch.cuda.synchronize()
+            o = out.cpu().numpy()
+            nested16.append({"sum": list(o[:4]), "sumsq": list(o[4:]), "n_paths": c3["n_paths"],
+                             "path_steps": c3["n_paths"] << l, "cost_seconds": e0.elapsed_time(e1) * 1e-3})
+        plain = _level_costs(M, call, c3["levels"], c3["n_paths"], M.MLMC_FP64, M.MLMC_EXACT, 0)
+        approx16 = _level_costs(M, call, c3["levels"], c3["n_paths"], M.MLMC_FP16, M.MLMC_APPROX_CUBIC16, 1)
+        rho = 2.0 ** -11
+        bound = [2 ** l * rho ** 2 * (1 + 0.05 * 2.0 ** -l) ** (2 * 2 ** l) * math.exp(0.04) * math.exp(0.14)
+                 for l in c3["levels"]]
+        rep["nested_fp16_cubic16_kahan_levels0to6_2p24"] = {
+            "nested_path_steps_per_s": rate(nested16), "approx_two_way_path_steps_per_s": rate(approx16),
+            "plain_fp64_path_steps_per_s": rate(plain),
+            "rounding_variance": var(nested16, 3), "rounding_variance_bound_B_l": bound,
+            "four_way_var": var(nested16, 1), "two_way_exact_var": var(nested16, 2),
+            "speedup_T_hat_over_T_bar": E.speedup_equal_variance(var(plain, 0), cost(plain), var(approx16, 0),
+                                                                 cost(approx16), var(nested16, 1), cost(nested16))}
 
-    # piecewise-constant variable (4096 cells, table lookup) against the piecewise-linear one:
-    # four-way variances, rates and the equal-variance speed-up over plain binary64 (call,
-    # levels 0..10, 2^20 paths)
-    plain_rows = _level_costs(M, call, LEVELS, N_PATHS, M.MLMC_FP64, M.MLMC_EXACT, 0)
-    pc = {}
-    for tag, prec, approx, nested, k in (
-            ("fp32_pconst", M.MLMC_FP32, M.MLMC_APPROX_PCONST4096, M.MLMC_NESTED_PCONST4096, 0),
-            ("fp32_pwl16", M.MLMC_FP32, M.MLMC_APPROX_PWL16, M.MLMC_NESTED_PWL16, 0),
-            ("fp16_pconst_kahan", M.MLMC_FP16, M.MLMC_APPROX_PCONST4096, M.MLMC_NESTED_PCONST4096, 1),
-            ("fp16_cubic16_kahan", M.MLMC_FP16, M.MLMC_APPROX_CUBIC16, M.MLMC_NESTED_CUBIC16, 1)):
-        a_rows = _level_costs(M, call, LEVELS, N_PATHS, prec, approx, k)
-        n_rows = _level_costs(M, call, LEVELS, N_PATHS, prec, nested, k)
-        pc[tag] = {"approx_two_way_path_steps_per_s": rate(a_rows), "nested_path_steps_per_s": rate(n_rows),
-                   "four_way_var": var(n_rows, 1),
-                   "speedup_T_hat_over_T_bar": E.speedup_equal_variance(
-                       var(plain_rows, 0), cost(plain_rows), var(a_rows, 0), cost(a_rows), var(n_rows, 1),
-                       cost(n_rows))}
-    rep["pconst4096_vs_dyadic_call_levels0to10_2p20"] = pc
+    if "batch" in legs:
+        # batched ragged sweep: 64 GBM parameter sets x levels 0..14, fp16 (l <= 6) / fp32 (l > 6)
+        psets = W.batch_parameter_sets(W.BATCH_PSETS, seed=0)
+        items = []
+        for p, d in enumerate(psets):
+            g = M.gbm(mu=d["mu"], sigma=d["sigma"])
+            for l in W.BATCH_LEVELS:
+                prec = M.MLMC_FP16 if l <= 6 else M.MLMC_FP32
+                items.append(M.item(g, l, W.batch_paths(l), prec, 1 if prec == M.MLMC_FP16 else 0, SEED, pset=p))
+        out = torch.zeros((len(items), 8), dtype=torch.float64, device="cuda")
+        plan = M.mlmc_batch_create(items, M.MLMC_RV_PWL16, out)
+        try:
+            best = M.mlmc_batch_autotune(plan, 2)
+            M.mlmc_batch_run(plan)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                M.mlmc_batch_run(plan)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            cfg, n_tasks = M.mlmc_batch_info(plan)
+            wave_s = M.mlmc_batch_item_times(plan, len(items))
+        finally:
+            M.mlmc_batch_destroy(plan)
+        steps = sum(it.n_paths << it.level for it in items)
+        resident = cfg.waves_per_cu * torch.cuda.get_device_properties(0).multi_processor_count
+        # device time attributed to items in proportion to their wavefront time; cost per sample
+        share = [w / sum(wave_s) * ms * 1e-3 for w in wave_s]
+        per_level = {}
+        for it, c in zip(items, share):
+            per_level.setdefault(it.level, []).append(c / it.n_paths)
+        rep["batch_64psets_levels0to14"] = {
+            "items": len(items), "tasks": n_tasks, "ms_per_sweep": ms, "path_steps": steps,
+            "path_steps_per_s": steps / ms * 1e3,
+            "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level],
+            "wave_slot_utilisation": sum(wave_s) / (resident * ms * 1e-3),
+            "cost_per_sample_s_by_level": [float(np.mean(per_level[l])) for l in sorted(per_level)]}
+
+    if "mlp" in legs:
+        # learned inverse CDF: train on 2^20 pairs, nested four-way levels 0..10 at 2^22 paths vs PWL16
+        params = torch.tensor(W.mlp_initial_params(0), dtype=torch.float32, device="cuda")
+        t0 = time.perf_counter()
+        hist = M.mlmc_mlp_train(M.mlp_cfg(n_pairs=W.MLP_TRAIN_PAIRS), params)
+        train_s = time.perf_counter() - t0
+        M.mlmc_mlp_load(params)
+        words = torch.arange(2 ** 20, dtype=torch.int64, device="cuda").mul(4096).add(2047).to(torch.int32)
+        zs = {}
+        for rv in (M.MLMC_RV_EXACT, M.MLMC_RV_MLP, M.MLMC_RV_PWL16):
+            z = torch.empty(2 ** 20, dtype=torch.float64, device="cuda")
+            M.mlmc_icdf(words, 2 ** 20, rv, M.MLMC_FP32, z)
+            zs[rv] = z
+        torch.cuda.synchronize()
+        mlp_rows = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_NESTED_MLP, 0)
+        pwl_rows = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0)
+        rep["mlp_nested_fp32_levels0to10_2p22"] = {
+            "train_seconds": train_s, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+            "mse_Z_minus_Ztilde": {"mlp": float(((zs[M.MLMC_RV_MLP] - zs[M.MLMC_RV_EXACT]) ** 2).mean()),
+                                   "pwl16": float(((zs[M.MLMC_RV_PWL16] - zs[M.MLMC_RV_EXACT]) ** 2).mean())},
+            "four_way_var": {"mlp": var(mlp_rows, 1), "pwl16": var(pwl_rows, 1)},
+            "nested_path_steps_per_s": {"mlp": rate(mlp_rows), "pwl16": rate(pwl_rows)}}
+    if "sweep" in legs:
+        # precision-width sweep (Figure 3's question): variance of the rounding difference
+        # X-_N - X~_N against the level for bfloat16 (8 bits), binary16 (11) and binary32 (24),
+        # without and with Kahan, piecewise cubic, payoff X_T, 2^18 paths per level
+        sweep = {}
+        gbm_x = M.gbm()
+        for name, prec in (("bf16", M.MLMC_BF16), ("fp16", M.MLMC_FP16), ("fp32", M.MLMC_FP32)):
+            for k in (0, 1):
+                v = []
+                for l in range(2, 11):
+                    args = M.level_args(gbm_x, l, 2 ** 18, prec, M.MLMC_APPROX_CUBIC16, k, SEED, diag=1)
+                    o = torch.zeros(8, dtype=torch.float64, device="cuda")
+                    M.mlmc_level_ex(args, o)
+                    torch.cuda.synchronize()
+                    t = o.cpu().numpy()
+                    v.append(E.level_stats(t[3], t[7], 2 ** 18)[1])
+                sweep["%s%s" % (name, "_kahan" if k else "")] = v
+        rho = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11, "fp32": 2.0 ** -24}
+        sweep["levels"] = list(range(2, 11))
+        sweep["bound_B_l"] = {n: [2 ** l * r * r * (1 + 0.05 * 2.0 ** -l) ** (2 * 2 ** l) * math.exp(0.04 + 0.14)
+                                  for l in range(2, 11)] for n, r in rho.items()}
+        rep["rounding_variance_precision_sweep_cubic_2p18"] = sweep
+
+    if "adaptive" in legs:
+        # adaptive MLMC with a per-level precision map from measured costs, against the plain
+        # binary64 estimator at the same accuracy (call payoff, eps = 1e-5)
+        mixed = D.adaptive_mlmc(call, 1e-5, seed=21)
+        adaptive_plain = D.adaptive_mlmc(call, 1e-5, options=(D.PLAIN_FP64,), seed=21)
+        with_pc = D.adaptive_mlmc(call, 1e-5, options=D.TABLE_OPTIONS, seed=21)
+        rep["adaptive_mlmc_call_eps1e-5_with_pconst"] = {
+            "estimate": with_pc["estimate"], "std_error": with_pc["std_error"], "L": with_pc["L"],
+            "choice": with_pc["choice"],
+            "predicted_speedup_vs_fp64": with_pc["predicted_seconds_single_option"]["fp64"] / with_pc["predicted_seconds"],
+            "measured_device_seconds": with_pc["measured_seconds"]}
+        rep["adaptive_mlmc_call_eps1e-5"] = {
+            "estimate": mixed["estimate"], "std_error": mixed["std_error"], "L": mixed["L"],
+            "choice": mixed["choice"], "predicted_speedup_vs_fp64": mixed["predicted_seconds_single_option"]["fp64"]
+            / mixed["predicted_seconds"],
+            "measured_device_seconds": mixed["measured_seconds"],
+            "plain_fp64_estimate": adaptive_plain["estimate"], "plain_fp64_std_error": adaptive_plain["std_error"],
+            "plain_fp64_measured_device_seconds": adaptive_plain["measured_seconds"],
+            "measured_speedup_vs_fp64": adaptive_plain["measured_seconds"] / mixed["measured_seconds"]}
+
+    if "milstein" in legs:
+        # Milstein (Section 4: order-1 strong convergence moves the work to the coarse levels):
+        # plain binary64 level variances against Euler-Maruyama's, nested rates, and the adaptive
+        # precision map at the same accuracy
+        mil = {}
+        lv = list(range(0, 11))
+        for tag, sch in (("em", M.MLMC_SCHEME_EM), ("milstein", M.MLMC_SCHEME_MILSTEIN)):
+            rows = [M.mlmc_level_run(M.level_args(call, l, 2 ** 20, M.MLMC_FP64, M.MLMC_EXACT, 0, SEED, scheme=sch))
+                    for l in lv]
+            mil["plain_fp64_var_" + tag] = var(rows, 0)
+        for tag, prec, mode, k in (("nested_fp32_pwl", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0),
+                                   ("nested_fp16_cubic_kahan", M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1),
+                                   ("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0)):
+            a = M.level_args(call, 10, 2 ** 20, prec, mode, k, SEED, scheme=M.MLMC_SCHEME_MILSTEIN)
+            M.mlmc_level_run(a)
+            r = M.mlmc_level_run(a)
+            mil["level10_path_steps_per_s_" + tag] = r["path_steps"] / r["cost_seconds"]
+        mil["levels"] = lv
+        m_mixed = D.adaptive_mlmc(call, 1e-5, seed=23, scheme=M.MLMC_SCHEME_MILSTEIN)
+        m_plain = D.adaptive_mlmc(call, 1e-5, options=(D.PLAIN_FP64,), seed=23, scheme=M.MLMC_SCHEME_MILSTEIN)
+        mil["adaptive_call_eps1e-5"] = {
+            "estimate": m_mixed["estimate"], "std_error": m_mixed["std_error"], "L": m_mixed["L"],
+            "choice": m_mixed["choice"],
+            "predicted_speedup_vs_fp64": m_mixed["predicted_seconds_single_option"]["fp64"]
+            / m_mixed["predicted_seconds"],
+            "measured_device_seconds": m_mixed["measured_seconds"],
+            "plain_fp64_estimate": m_plain["estimate"], "plain_fp64_measured_device_seconds": m_plain["measured_seconds"],
+            "measured_speedup_vs_fp64": m_plain["measured_seconds"] / m_mixed["measured_seconds"],
+            "em_plain_fp64_measured_device_seconds": adaptive_plain["measured_seconds"] if adaptive_plain else None}
+        rep["milstein_call"] = mil
+
+    if "pconst" in legs:
+        # piecewise-constant variable (4096 cells, table lookup) against the piecewise-linear one:
+        # four-way variances, rates and the equal-variance speed-up over plain binary64 (call,
+        # levels 0..10, 2^20 paths)
+        plain_rows = _level_costs(M, call, LEVELS, N_PATHS, M.MLMC_FP64, M.MLMC_EXACT, 0)
+        pc = {}
+        for tag, prec, approx, nested, k in (
+                ("fp32_pconst", M.MLMC_FP32, M.MLMC_APPROX_PCONST4096, M.MLMC_NESTED_PCONST4096, 0),
+                ("fp32_pwl16", M.MLMC_FP32, M.MLMC_APPROX_PWL16, M.MLMC_NESTED_PWL16, 0),
+                ("fp16_pconst_kahan", M.MLMC_FP16, M.MLMC_APPROX_PCONST4096, M.MLMC_NESTED_PCONST4096, 1),
+                ("fp16_cubic16_kahan", M.MLMC_FP16, M.MLMC_APPROX_CUBIC16, M.MLMC_NESTED_CUBIC16, 1)):
+            a_rows = _level_costs(M, call, LEVELS, N_PATHS, prec, approx, k)
+            n_rows = _level_costs(M, call, LEVELS, N_PATHS, prec, nested, k)
+            pc[tag] = {"approx_two_way_path_steps_per_s": rate(a_rows), "nested_path_steps_per_s": rate(n_rows),
+                       "four_way_var": var(n_rows, 1),
+                       "speedup_T_hat_over_T_bar": E.speedup_equal_variance(
+                           var(plain_rows, 0), cost(plain_rows), var(a_rows, 0), cost(a_rows), var(n_rows, 1),
+                           cost(n_rows))}
+        rep["pconst4096_vs_dyadic_call_levels0to10_2p20"] = pc
     np.seterr(all="ignore")
     return rep
 
