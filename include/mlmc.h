@@ -231,13 +231,14 @@ typedef struct {
 
 /* launch shape of a batch (0 in a field selects the default or the autotuned value) */
 typedef struct {
-    int32_t waves_per_cu;    /* resident wavefronts per CU of the persistent grid: 4..32   */
+    int32_t waves_per_cu;    /* wavefronts per CU of the persistent grid (8-wave blocks;  */
+                             /* the count is rounded down to whole blocks): 4..32         */
     int32_t task_steps;      /* fine steps per task at level 0 (tasks of level l hold      */
                              /* max(1, task_steps >> l) chunks): 1..2^20                 */
     int32_t priority_level;  /* tasks of level >= this run at raised wave priority; 25=off */
     int32_t coop_level;      /* binary32 items of level >= this (2..25; 25 = off) run each   */
-                             /* chunk on a whole 4-wave block: three waves draw the       */
-                             /* variables of the next 12 steps into LDS while one wave    */
+                             /* chunk on a whole 8-wave block: seven waves draw the       */
+                             /* variables of the next 28 steps into LDS while one wave    */
                              /* advances the paths (same operations, same bits)           */
 } mlmc_batch_cfg_t;
 

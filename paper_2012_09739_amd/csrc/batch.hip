@@ -12,10 +12,10 @@
 //
 // Cooperative chunks: the chunks of the deepest binary32 items (level >= coop_level) are
 // serial chains of up to 2^24 steps, and one wavefront alone runs them latency bound.  Each
-// block first pops such chunks from a block queue and runs one chunk with all four waves:
-// three producer waves draw the uniforms and both inverse CDFs for the next phase of 12
-// steps into an LDS ring while the consumer wave advances the four coupled paths through
-// the current phase, one barrier per phase.  The consumer performs exactly the operations
+// block (eight waves) first pops such chunks from a block queue and runs one chunk with all
+// its waves: seven producer waves draw the uniforms and both inverse CDFs for the next phase
+// of 28 steps into an LDS ring while the consumer wave advances the four coupled paths
+// through the current phase, one barrier per phase.  The consumer performs exactly the operations
 // of the single-wave code in the same order, so every sum keeps its bits.
 #include <hip/hip_runtime.h>
 
@@ -84,13 +84,13 @@ __global__ void batch_reset(uint32_t* counter, unsigned long long* ticks, uint32
     for (uint32_t k = i; k < n_items; k += gridDim.x * blockDim.x) ticks[k] = 0ull;
 }
 
-constexpr int kBatchBlock = 256;
-constexpr int kCoopProducers = kBatchBlock / kWave - 1;  // waves 1..3 of a block
+constexpr int kBatchBlock = 512;                         // eight waves
+constexpr int kCoopProducers = kBatchBlock / kWave - 1;  // waves 1..7 of a block
 constexpr int kCoopSteps = 4 * kCoopProducers;            // fine steps per phase: one Philox call per producer
 
 // One cooperative chunk of a nested binary32 item (n_steps >= 4, a multiple of 4) run by
-// the whole block.  Phase f covers fine steps [12 f, 12 f + 12): producer wave p draws
-// Philox call 3 f + p - 1 and writes its four exact (binary64) and approximate (binary32)
+// the whole block.  Phase f covers fine steps [28 f, 28 f + 28): producer wave p draws
+// Philox call 7 f + p - 1 and writes its four exact (binary64) and approximate (binary32)
 // variables into ring slot f & 1; the consumer, wave 0, reads slot f & 1 while the
 // producers fill slot (f + 1) & 1, and a barrier closes every phase (the same number of
 // barriers in every wave).  The consumer's updates and payoff terms are those of run_chunk
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))
     stage_exact_table(s_ex_raw, exact_tab);
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    // cooperative chunks first: the block pops one, all four waves run it (block-uniform loop)
+    // cooperative chunks first: the block pops one, all its waves run it (block-uniform loop)
     for (;;) {
         if (threadIdx.x == 0) s_pop = atomicAdd(&counter[1], 1u);
         __syncthreads();
@@ -635,24 +635,25 @@ int mlmc_batch_autotune(mlmc_batch_t* plan, int repeats, mlmc_batch_cfg_t* best)
         (void)hipEventDestroy(e0);
         return rc;
     }
-    // wavefronts per CU: multiples of the 4-wave block up to what the kernel's register use
+    // wavefronts per CU: multiples of the 8-wave block up to what the kernel's register use
     // lets reside at once (a persistent wave that cannot start before the queue drains is idle)
     int blocks_per_cu = 0;
     if (plan->rv == MLMC_RV_CUBIC16)
-        rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, batch_kernel<MLMC_RV_CUBIC16>, 256, 0),
+        rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, batch_kernel<MLMC_RV_CUBIC16>, kBatchBlock, 0),
                    "occupancy query");
     else
-        rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, batch_kernel<MLMC_RV_PWL16>, 256, 0),
+        rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, batch_kernel<MLMC_RV_PWL16>, kBatchBlock, 0),
                    "occupancy query");
     if (rc) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         return rc;
     }
+    constexpr int kBlockWaves = kBatchBlock / kWave;
     std::vector<int> waves;
-    for (int w = 8; w <= 32; w += 4)
-        if (w <= 4 * blocks_per_cu) waves.push_back(w);
-    if (waves.empty()) waves.push_back(4 * std::max(1, blocks_per_cu));
+    for (int w = kBlockWaves; w <= 32; w += kBlockWaves)
+        if (w <= kBlockWaves * blocks_per_cu) waves.push_back(w);
+    if (waves.empty()) waves.push_back(kBlockWaves * std::max(1, blocks_per_cu));
     const int steps[] = {64, 256, 1024};
     const int prios[] = {12, 25};
     const int coops[] = {11, 12, 13, 25};
