@@ -392,7 +392,8 @@ def reports(M, E, torch, legs=REPORT_LEGS):
             "estimate": with_pc["estimate"], "std_error": with_pc["std_error"], "L": with_pc["L"],
             "choice": with_pc["choice"],
             "predicted_speedup_vs_fp64": with_pc["predicted_seconds_single_option"]["fp64"] / with_pc["predicted_seconds"],
-            "measured_device_seconds": with_pc["measured_seconds"]}
+            "measured_device_seconds": with_pc["measured_seconds"],
+            "measured_device_seconds_one_by_one": with_pc["measured_seconds_one_by_one"]}
         rep["adaptive_mlmc_call_eps1e-5"] = {
             "estimate": mixed["estimate"], "std_error": mixed["std_error"], "L": mixed["L"],
             "choice": mixed["choice"], "predicted_speedup_vs_fp64": mixed["predicted_seconds_single_option"]["fp64"]
@@ -400,7 +401,9 @@ def reports(M, E, torch, legs=REPORT_LEGS):
             "measured_device_seconds": mixed["measured_seconds"],
             "plain_fp64_estimate": adaptive_plain["estimate"], "plain_fp64_std_error": adaptive_plain["std_error"],
             "plain_fp64_measured_device_seconds": adaptive_plain["measured_seconds"],
-            "measured_speedup_vs_fp64": adaptive_plain["measured_seconds"] / mixed["measured_seconds"]}
+            "measured_speedup_vs_fp64": adaptive_plain["measured_seconds"] / mixed["measured_seconds"],
+            "measured_device_seconds_one_by_one": mixed["measured_seconds_one_by_one"],
+            "plain_fp64_measured_device_seconds_one_by_one": adaptive_plain["measured_seconds_one_by_one"]}
 
     if "milstein" in legs:
         # Milstein (Section 4: order-1 strong convergence moves the work to the coarse levels):
@@ -430,6 +433,8 @@ def reports(M, E, torch, legs=REPORT_LEGS):
             "measured_device_seconds": m_mixed["measured_seconds"],
             "plain_fp64_estimate": m_plain["estimate"], "plain_fp64_measured_device_seconds": m_plain["measured_seconds"],
             "measured_speedup_vs_fp64": m_plain["measured_seconds"] / m_mixed["measured_seconds"],
+            "measured_device_seconds_one_by_one": m_mixed["measured_seconds_one_by_one"],
+            "plain_fp64_measured_device_seconds_one_by_one": m_plain["measured_seconds_one_by_one"],
             "em_plain_fp64_measured_device_seconds": adaptive_plain["measured_seconds"] if adaptive_plain else None}
         rep["milstein_call"] = mil
 

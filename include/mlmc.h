@@ -165,6 +165,20 @@ int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision
  * device time of the call.  Errors as mlmc_level. */
 int mlmc_level_run(const mlmc_level_args_t* args, mlmc_result_t* out);
 
+/* Several level calls at once, synchronously: the final sampling of an MLMC estimate
+ * (Section 3) draws every term of every level, and a deep level with few samples is a few
+ * long serial paths that leave most of the GPU idle.  The calls are issued longest chain
+ * first (level, then n_paths), dealt round-robin over four library streams, so that such
+ * calls overlap the shallow levels' many short paths.  args: host, n_calls (1..4096) argument
+ * sets, each validated as for mlmc_level_run before anything is launched (the message names
+ * the failing call).  out: host, n_calls results, each equal to what mlmc_level_run returns
+ * for the same arguments except cost_seconds, the device time from the call's start to its
+ * end while it shared the GPU.  span_seconds: host, may be NULL: device time from the first
+ * call's start to the last call's end.  Uses its own streams and device memory (one
+ * workspace per call, kept for the next set); sets that overlap on one device race. */
+int mlmc_level_set_run(const mlmc_level_args_t* args, int n_calls, mlmc_result_t* out,
+                       double* span_seconds);
+
 /* Asynchronous level call on hip_stream.  args: host.  d_out: device, 8 doubles
  * (sum[0..3], sumsq[0..3]) written when the stream reaches the call.  d_workspace:
  * device scratch of at least mlmc_level_workspace_bytes(args) bytes (8-byte aligned; it

@@ -6,9 +6,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
+#include <numeric>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 #include "mlp.h"
@@ -108,6 +111,9 @@ double rounded_to(int precision, double c) {
 }
 
 // ---- per-device state -------------------------------------------------------------------
+constexpr int kSetStreams = 4;     // streams of a level set (the hardware queues of a process)
+constexpr int kMaxSetCalls = 4096;  // calls per level set
+
 struct DevState {
     bool ready = false;
     int n_cu = 256;
@@ -122,6 +128,12 @@ struct DevState {
     float* mlp = nullptr;               // MLP inference image (binary16 values as binary32)
     void* exact_tab = nullptr;          // ExactTable: log cells and piecewise coefficients of g
     bool mlp_loaded = false;
+    // level sets: their own streams, events (two per call and two per set) and device memory
+    // (result slots, then one workspace per call), created on first use
+    hipStream_t set_stream[kSetStreams] = {nullptr};
+    std::vector<hipEvent_t> set_events;
+    void* set_mem = nullptr;
+    size_t set_mem_bytes = 0;
 };
 
 std::mutex g_mutex;
@@ -488,6 +500,10 @@ int mlmc_shutdown(void) {
         if (st.ev0) (void)hipEventDestroy(st.ev0);
         if (st.ev1) (void)hipEventDestroy(st.ev1);
         if (st.stream) (void)hipStreamDestroy(st.stream);
+        for (hipStream_t& q : st.set_stream)
+            if (q) (void)hipStreamDestroy(q);
+        for (hipEvent_t ev : st.set_events) (void)hipEventDestroy(ev);
+        if (st.set_mem) (void)hipFree(st.set_mem);
     }
     g_devs.clear();
     (void)hipSetDevice(cur);
@@ -551,6 +567,110 @@ int mlmc_level_run(const mlmc_level_args_t* args, mlmc_result_t* out) {
     out->n_paths = args->n_paths;
     out->path_steps = args->n_paths << args->level;
     out->cost_seconds = 1e-3 * (double)ms;
+    return MLMC_OK;
+}
+
+int mlmc_level_set_run(const mlmc_level_args_t* args, int n_calls, mlmc_result_t* out, double* span_seconds) {
+    if (!args) return fail(MLMC_EINVAL, "args is NULL");
+    if (!out) return fail(MLMC_EINVAL, "out is NULL");
+    if (n_calls < 1 || n_calls > kMaxSetCalls) return fail(MLMC_EINVAL, "n_calls must be 1..%d", kMaxSetCalls);
+    std::vector<Variant> v(n_calls);
+    for (int i = 0; i < n_calls; ++i) {
+        const int rc = validate_args(&args[i], &v[i]);
+        if (rc) return fail(rc, "call %d: %s", i, g_error.c_str());
+    }
+    DevState* st;
+    int rc = device_state(&st);
+    if (rc) return rc;
+    for (int i = 0; i < n_calls; ++i)
+        if (v[i].rv == MLMC_RV_MLP && !st->mlp_loaded)
+            return fail(MLMC_EUNSUPPORTED, "call %d: MLMC_RV_MLP needs weights: call mlmc_mlp_load first", i);
+    // device memory: n_calls result slots of 8 doubles, then each call's workspace (256-byte aligned)
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    std::vector<size_t> ws_off(n_calls);
+    size_t total = up((size_t)n_calls * kPartial * sizeof(double));
+    for (int i = 0; i < n_calls; ++i) {
+        ws_off[i] = total;
+        total += up(level_workspace_bytes(n_chunks_of(&args[i])));
+    }
+    hipError_t e;
+    for (hipStream_t& q : st->set_stream)
+        if (!q && (e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreate");
+    while (st->set_events.size() < (size_t)(2 * n_calls + kSetStreams + 1)) {
+        hipEvent_t ev;
+        if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        st->set_events.push_back(ev);
+    }
+    if (total > st->set_mem_bytes) {
+        if (st->set_mem) {
+            (void)hipFree(st->set_mem);  // the previous set has completed (every set is synchronous)
+            st->set_mem = nullptr;
+            st->set_mem_bytes = 0;
+        }
+        if ((e = hipMalloc(&st->set_mem, total)) != hipSuccess)
+            return fail(MLMC_ENOMEM, "hipMalloc of %zu level-set bytes failed", total);
+        st->set_mem_bytes = total;
+    }
+    unsigned char* mem = (unsigned char*)st->set_mem;
+    double* results = (double*)mem;
+    hipEvent_t* ev = st->set_events.data();  // [2i, 2i+1]: call i; then the set's begin, joins, end
+    hipEvent_t ev_begin = ev[2 * n_calls], ev_end = ev[2 * n_calls + kSetStreams];
+    // the longest serial chains first (level, then samples), dealt round-robin over the
+    // streams, so that the deep levels' few long paths overlap the shallow levels' many short ones
+    std::vector<int> order(n_calls);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (args[a].level != args[b].level) return args[a].level > args[b].level;
+        return args[a].n_paths > args[b].n_paths;
+    });
+    hipStream_t s0 = st->set_stream[0];
+    if ((e = hipEventRecord(ev_begin, s0)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (int q = 1; q < kSetStreams; ++q)
+        if ((e = hipStreamWaitEvent(st->set_stream[q], ev_begin, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    for (int k = 0; k < n_calls && rc == MLMC_OK; ++k) {
+        const int i = order[k];
+        hipStream_t q = st->set_stream[k % kSetStreams];
+        if ((e = hipEventRecord(ev[2 * i], q)) != hipSuccess) {
+            rc = hip_fail(e, "hipEventRecord");
+            break;
+        }
+        rc = enqueue_level(*st, &args[i], v[i], results + (size_t)i * kPartial, (double*)(mem + ws_off[i]), nullptr,
+                           nullptr, nullptr, nullptr, nullptr, q);
+        if (rc == MLMC_OK && (e = hipEventRecord(ev[2 * i + 1], q)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+    }
+    // join the streams into the first one (also after a failed launch, so nothing is left running)
+    for (int q = 1; q < kSetStreams; ++q) {
+        if ((e = hipEventRecord(ev[2 * n_calls + q], st->set_stream[q])) != hipSuccess ||
+            (e = hipStreamWaitEvent(s0, ev[2 * n_calls + q], 0)) != hipSuccess) {
+            for (hipStream_t r : st->set_stream) (void)hipStreamSynchronize(r);
+            return rc ? rc : hip_fail(e, "stream join");
+        }
+    }
+    if ((e = hipEventRecord(ev_end, s0)) != hipSuccess && rc == MLMC_OK) rc = hip_fail(e, "hipEventRecord");
+    if ((e = hipStreamSynchronize(s0)) != hipSuccess && rc == MLMC_OK) rc = hip_fail(e, "hipStreamSynchronize");
+    if (rc) return rc;
+    std::vector<double> h((size_t)n_calls * kPartial);
+    if ((e = hipMemcpy(h.data(), results, h.size() * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy");
+    for (int i = 0; i < n_calls; ++i) {
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        bool m[4];
+        term_mask(v[i], m);
+        for (int t = 0; t < kTerms; ++t) {
+            out[i].sum[t] = m[t] ? h[(size_t)i * kPartial + t] : NAN;
+            out[i].sumsq[t] = m[t] ? h[(size_t)i * kPartial + kTerms + t] : NAN;
+        }
+        out[i].n_paths = args[i].n_paths;
+        out[i].path_steps = args[i].n_paths << args[i].level;
+        out[i].cost_seconds = 1e-3 * (double)ms;
+    }
+    if (span_seconds) {
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, ev_begin, ev_end)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        *span_seconds = 1e-3 * (double)ms;
+    }
     return MLMC_OK;
 }
 

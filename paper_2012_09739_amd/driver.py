@@ -141,29 +141,38 @@ def pilot_level(sde, level, options, n, seed, scheme=M.MLMC_SCHEME_EM):
     return p
 
 
+def _term_call(sde, level, opt, term_index, n, seed, scheme=M.MLMC_SCHEME_EM):
+    """Arguments of the level call that draws n samples of one term of one option, and the
+    index of that term in the call's result."""
+    if not opt.nested:
+        mode, kahan, t = M.MLMC_EXACT, 0, 0
+    elif term_index == 0:
+        mode, kahan, t = opt.rv, opt.kahan, 0
+    else:
+        mode, kahan, t = opt.rv + 4, opt.kahan, 1
+    return M.level_args(sde, level, n, opt.precision, mode, kahan, seed, scheme=scheme), t
+
+
 def _run_term(sde, level, opt, term_index, n, seed, scheme=M.MLMC_SCHEME_EM):
     """n samples of one term of one option; returns (sum, sum of squares, n, device seconds)."""
-    if not opt.nested:
-        r = _level(sde, level, n, opt.precision, M.MLMC_EXACT, 0, seed, scheme)
-        t = 0
-    elif term_index == 0:
-        r = _level(sde, level, n, opt.precision, opt.rv, opt.kahan, seed, scheme)
-        t = 0
-    else:
-        r = _level(sde, level, n, opt.precision, opt.rv + 4, opt.kahan, seed, scheme)
-        t = 1
+    args, t = _term_call(sde, level, opt, term_index, n, seed, scheme)
+    r = M.mlmc_level_run(args)
     return r["sum"][t], r["sumsq"][t], n, r["cost_seconds"]
 
 
 def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pilot=2 ** 19, seed=0,
-                  max_samples=2 ** 32, scheme=M.MLMC_SCHEME_EM):
+                  max_samples=2 ** 32, scheme=M.MLMC_SCHEME_EM, concurrent=True):
     """Adaptive MLMC to root-mean-square error eps with a per-level choice among options.
 
     Returns a dict: estimate, its standard error, L, per-level choice, samples per term,
     the predicted device time of the chosen mixture and of each single option used at every
     level (the plain binary64 estimator among them), and the measured device time of the
-    final sampling (pilot runs excluded; each call also pays a fixed launch and reduction
-    cost of some 20 us that the per-sample model leaves out)."""
+    final sampling (pilot runs excluded).  concurrent: the final sampling is one level set
+    (mlmc_level_set_run: every term's call issued together, deep levels first, over several
+    streams) and the measured time is its span; otherwise the calls run one after another
+    and the measured time is the sum of their device times, each with a fixed launch and
+    reduction cost of some 20 us that the per-sample model leaves out.  The samples, and so
+    the estimate, are the same either way."""
     by_name = {o.name: o for o in options}
     pilots = []
     level = 0
@@ -187,10 +196,19 @@ def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pil
     final_seed = seed + 1
     sums = {}
     device_s = 0.0
-    for (l, name, j), n in zip(where, counts):
-        s, q, m, t = _run_term(sde, l, by_name[name], j, n, final_seed, scheme)
-        sums[(l, j)] = (s, q, m)
-        device_s += t
+    one_by_one = None
+    if concurrent:
+        calls = [_term_call(sde, l, by_name[name], j, n, final_seed, scheme) for (l, name, j), n in zip(where, counts)]
+        results, device_s = M.mlmc_level_set_run([a for a, _ in calls])
+        for (l, _, j), n, (_, t), r in zip(where, counts, calls, results):
+            sums[(l, j)] = (r["sum"][t], r["sumsq"][t], n)
+        # the same calls once more, one after another, for the device time without overlap
+        one_by_one = math.fsum(M.mlmc_level_run(a)["cost_seconds"] for a, _ in calls)
+    else:
+        for (l, name, j), n in zip(where, counts):
+            s, q, m, t = _run_term(sde, l, by_name[name], j, n, final_seed, scheme)
+            sums[(l, j)] = (s, q, m)
+            device_s += t
     estimate, var = 0.0, 0.0
     parts = []
     for (l, j), (s, q, m) in sorted(sums.items()):
@@ -205,5 +223,5 @@ def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pil
     return {"estimate": estimate, "std_error": math.sqrt(var), "L": L, "choice": choice,
             "samples": {"%d/%s/%d" % w: n for w, n in zip(where, counts)},
             "predicted_seconds": predicted_time(flat, eps), "predicted_seconds_single_option": single,
-            "measured_seconds": device_s,
+            "measured_seconds": device_s, "measured_seconds_one_by_one": one_by_one,
             "per_level_a": [{k: cost_weight(v) for k, v in p.terms.items()} for p in pilots]}

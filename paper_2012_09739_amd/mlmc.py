@@ -76,6 +76,8 @@ _SIGNATURES = {
     "mlmc_level": (ctypes.c_int, [ctypes.POINTER(mlmc_gbm_t), ctypes.c_int, ctypes.c_uint64, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(mlmc_result_t)]),
     "mlmc_level_run": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), ctypes.POINTER(mlmc_result_t)]),
+    "mlmc_level_set_run": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), ctypes.c_int,
+                                          ctypes.POINTER(mlmc_result_t), ctypes.POINTER(ctypes.c_double)]),
     "mlmc_level_ex": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), _P, _P, ctypes.c_size_t, _P]),
     "mlmc_level_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(mlmc_level_args_t)]),
     "mlmc_paths": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), _P, _P, _P, _P, _P, _P]),
@@ -184,6 +186,17 @@ def mlmc_level_run(args):
     out = mlmc_result_t()
     _check(lib().mlmc_level_run(ctypes.byref(args), ctypes.byref(out)))
     return _result_dict(out)
+
+
+def mlmc_level_set_run(args_list):
+    """Level calls issued together over the library's streams; returns (list of result dicts
+    as mlmc_level_run, device seconds from the first start to the last end)."""
+    n = len(args_list)
+    arr = (mlmc_level_args_t * n)(*args_list)
+    res = (mlmc_result_t * n)()
+    span = ctypes.c_double(0.0)
+    _check(lib().mlmc_level_set_run(arr, n, res, ctypes.byref(span)))
+    return [_result_dict(r) for r in res], span.value
 
 
 def mlmc_level_workspace_bytes(args):

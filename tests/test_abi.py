@@ -138,3 +138,17 @@ def test_batch_validation_before_device():
             M.mlmc_batch_create([M.item(s, 3, 10, M.MLMC_FP32)], M.MLMC_RV_PWL16, 1, cfg)
         assert e.value.code == M.MLMC_EINVAL
     assert M.lib().mlmc_batch_destroy(None) == M.MLMC_OK
+
+
+def test_level_set_validation_before_device():
+    lib = M.lib()
+    good = M.level_args(M.gbm(), 3, 100, M.MLMC_FP32, M.MLMC_NESTED_PWL16)
+    bad = M.level_args(M.gbm(), 3, 100, M.MLMC_FP32, M.MLMC_EXACT)  # the plain estimator is binary64
+    res = (M.mlmc_result_t * 2)()
+    arr = (M.mlmc_level_args_t * 2)(good, bad)
+    assert lib.mlmc_level_set_run(arr, 2, res, None) == M.MLMC_EINVAL
+    assert "call 1" in M.mlmc_last_error()
+    assert lib.mlmc_level_set_run(arr, 0, res, None) == M.MLMC_EINVAL
+    assert lib.mlmc_level_set_run(arr, 4097, res, None) == M.MLMC_EINVAL
+    assert lib.mlmc_level_set_run(None, 1, res, None) == M.MLMC_EINVAL
+    assert lib.mlmc_level_set_run(arr, 1, None, None) == M.MLMC_EINVAL

@@ -72,10 +72,20 @@ class FakeLevels:
             q[k] = n * (var + mean * mean)
         return {"sum": s, "sumsq": q, "n_paths": n, "path_steps": n << level, "cost_seconds": c * n}
 
+    def set_run(self, args_list):
+        """Stands in for mlmc_level_set_run: the calls as if run side by side."""
+        res = [self(a) for a in args_list]
+        return res, max(r["cost_seconds"] for r in res)
+
+
+def patch(monkeypatch, fake):
+    monkeypatch.setattr(D.M, "mlmc_level_run", fake)
+    monkeypatch.setattr(D.M, "mlmc_level_set_run", fake.set_run)
+
 
 def test_driver_orchestration_with_synthetic_levels(monkeypatch):
     fake = FakeLevels()
-    monkeypatch.setattr(D.M, "mlmc_level_run", fake)
+    patch(monkeypatch, fake)
     eps = 1e-3
     out = D.adaptive_mlmc(M.gbm(), eps, n_pilot=1 << 16)
     L = out["L"]
@@ -98,6 +108,24 @@ def test_driver_orchestration_with_synthetic_levels(monkeypatch):
 
 def test_driver_passes_the_scheme_to_every_call(monkeypatch):
     fake = FakeLevels()
-    monkeypatch.setattr(D.M, "mlmc_level_run", fake)
+    patch(monkeypatch, fake)
     D.adaptive_mlmc(M.gbm(), 1e-3, n_pilot=1 << 10, scheme=M.MLMC_SCHEME_MILSTEIN)
     assert fake.schemes == {M.MLMC_SCHEME_MILSTEIN}
+
+
+def test_concurrent_final_sampling_draws_the_same_samples(monkeypatch):
+    fake = FakeLevels()
+    patch(monkeypatch, fake)
+    a = D.adaptive_mlmc(M.gbm(), 1e-3, n_pilot=1 << 12, concurrent=True)
+    final_a = [c for c in fake.calls if c[-1] == 1]
+    fake.calls.clear()
+    b = D.adaptive_mlmc(M.gbm(), 1e-3, n_pilot=1 << 12, concurrent=False)
+    final_b = [c for c in fake.calls if c[-1] == 1]
+    assert sorted(final_a) == sorted(final_b * 2)    # the set, then the same calls timed one by one
+    assert a["estimate"] == b["estimate"] and a["std_error"] == b["std_error"]
+    # one set: the span is the longest call; one after another: the sum of the calls
+    costs = [fake(D._term_call(M.gbm(), l, D.NESTED_FP16_KAHAN, j, n, 1)[0])["cost_seconds"]
+             for (l, j), n in ((tuple(int(x) for x in k.split("/")[::2]), n) for k, n in b["samples"].items())]
+    assert a["measured_seconds"] == pytest.approx(max(costs))
+    assert b["measured_seconds"] == pytest.approx(sum(costs))
+    assert a["measured_seconds_one_by_one"] == pytest.approx(sum(costs))

@@ -1,0 +1,68 @@
+"""GPU tests of level sets (several level calls issued together over the library's streams):
+every call's sums equal the single call's bit for bit, whatever the mix of precisions,
+modes, schemes and sizes, also when the set's device memory grows between sets; and a set
+whose calls overlap well takes less device time than the same calls one after another."""
+
+import numpy as np
+import pytest
+
+from gpu_util import torch_cuda
+
+import paper_2012_09739_amd as M
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix(scale):
+    call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
+    return [
+        M.level_args(call, 9, 300 * scale + 7, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1, 3),
+        M.level_args(M.gbm(), 0, 50000 * scale, M.MLMC_FP64, M.MLMC_EXACT, 0, 3),
+        M.level_args(call, 1, 4097 * scale, M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1, 3),
+        M.level_args(call, 6, 2000 * scale + 1, M.MLMC_FP16, M.MLMC_APPROX_PCONST4096, 1, 3, diag=1),
+        M.level_args(call, 4, 0, M.MLMC_FP32, M.MLMC_APPROX_PWL16, 0, 3),
+        M.level_args(call, 5, 999 * scale, M.MLMC_FP64, M.MLMC_EXACT, 0, 3, scheme=M.MLMC_SCHEME_MILSTEIN),
+        M.level_args(call, 7, 1234 * scale, M.MLMC_BF16, M.MLMC_NESTED_PWL16, 1, 3, pset=5),
+        M.level_args(call, 3, 777 * scale, M.MLMC_FP32, M.MLMC_APPROX_CUBIC16, 0, 9, stream=7, path_offset=123),
+    ]
+
+
+def _same(a, b):
+    for k in ("sum", "sumsq"):
+        np.testing.assert_array_equal(np.array(a[k]), np.array(b[k]))
+    assert a["n_paths"] == b["n_paths"] and a["path_steps"] == b["path_steps"]
+
+
+@pytest.mark.parametrize("scale", [1, 3])
+def test_set_equals_single_calls(scale):
+    torch_cuda()
+    calls = _mix(scale)
+    got, span = M.mlmc_level_set_run(calls)
+    assert span > 0
+    for a, r in zip(calls, got):
+        _same(r, M.mlmc_level_run(a))
+        assert r["cost_seconds"] > 0
+
+
+def test_set_of_one_and_growing_sets():
+    torch_cuda()
+    calls = _mix(1)
+    one, _ = M.mlmc_level_set_run(calls[:1])
+    _same(one[0], M.mlmc_level_run(calls[0]))
+    big = [M.level_args(M.gbm(), l, 2 ** 16, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, 1) for l in range(11)]
+    got, _ = M.mlmc_level_set_run(big)
+    for a, r in zip(big, got):
+        _same(r, M.mlmc_level_run(a))
+
+
+def test_overlap_shortens_the_device_time():
+    # a few long serial paths (level 12, 4 chunks) next to many short ones: side by side the
+    # deep call's chains hide behind the shallow calls' throughput
+    torch_cuda()
+    call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
+    calls = [M.level_args(call, 12, 256, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, 4)] + \
+            [M.level_args(call, l, 2 ** 20, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, 4) for l in (2, 3, 4)]
+    M.mlmc_level_set_run(calls)
+    _, span = M.mlmc_level_set_run(calls)
+    one_by_one = sum(M.mlmc_level_run(a)["cost_seconds"] for a in calls)
+    assert span < one_by_one, (span, one_by_one)
