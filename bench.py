@@ -41,18 +41,18 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 # binary32 piecewise-linear kernel with Kahan updates, for the minimal operation sequence of
 # this formulation:
 #   Philox4x32-10, a quarter call: 4 products x 2 + 4.5 three-input xors x 1/2     10.25
-#   exact inverse CDF: 24 binary64 operations (x, y = 1 - x^2, table log with a
-#     degree-3 log1p, interval and coordinate of g, degree-5 piece, x g) + 4
-#     32-bit ones x 1/2                                                            26.0
+#   exact inverse CDF: 13 binary64 operations (x, y = 1 - x^2, t = y - c, the two
+#     binary32 coefficients widened, degree-6 cell polynomial, x G) + 5 32-bit
+#     ones x 1/2 (key, cell index, address, cell centre, deep-cell test)          15.5
 #   binary64 fine and half coarse EM update in the product form of GBM,
 #     X = fma(X, fma(cb, Z, ca), X): fine 2; coarse Z sum + 2 = 3, half of it      3.5
 #   piecewise-linear inverse CDF, binary32: 13 32-bit operations x 1/2             6.5
 #   binary32 fine and half coarse Kahan EM update: (8 + 9/2) x 1/2                 6.25
-ALG_OPS_PER_STEP = 52.5
+ALG_OPS_PER_STEP = 42.0
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (129.5 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "139bdf37887252ba353f718c799a788b86bfc4a8ef1a163dd09f83c3aa73a6b3"
+TRAFFIC_BYTES_PER_LAUNCH = (215.9375 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "d3a1289afa8c8f270fbb8139d780141be7ae2460cd2d196a25c6636c38c9571b"
 KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
                   "icdf_exact_coeffs.h")
 

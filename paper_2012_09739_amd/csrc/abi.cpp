@@ -126,7 +126,7 @@ struct DevState {
     size_t scratch_bytes = 0;
     double* out8 = nullptr;             // result slot of the synchronous entry point
     float* mlp = nullptr;               // MLP inference image (binary16 values as binary32)
-    void* exact_tab = nullptr;          // ExactTable: log cells and piecewise coefficients of g
+    void* exact_tab = nullptr;          // ExactTable: rows of the exact variable, log cells
     bool mlp_loaded = false;
     // level sets: their own streams, events (two per call and two per set) and device memory
     // (result slots, then one workspace per call), created on first use
@@ -225,19 +225,33 @@ int device_state(DevState** out) {
         if ((e = hipMalloc(&st.out8, kPartial * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
         if ((e = hipMalloc(&st.mlp, kMlpImage * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
         {
-            // cell i covers the frexp mantissa m in [(1 + i/256)/2, (1 + (i+1)/256)/2):
-            // f = R(1/c), l = R(-log f), c the centre; then the generated piecewise
-            // coefficients of g, coefficient-major
+            // log cells (the learned variable's input): cell i covers the frexp mantissa m in
+            // [(1 + i/256)/2, (1 + (i+1)/256)/2): f = R(1/c), l = R(-log f), c the centre; then
+            // the generated rows of G, row k for the key kKeyMin + k: the deep ones as rows, the
+            // top ones in three arrays
             static ExactTable h;
             for (int i = 0; i < kLogCells; ++i) {
                 const double c = 0.5 + (i + 0.5) / (2.0 * kLogCells);
                 const double f = 1.0 / c;
-                h.log[i].f = f;
-                h.log[i].l = (double)(-std::log((long double)f));
+                h.lds.log[i].f = f;
+                h.lds.log[i].l = (double)(-std::log((long double)f));
             }
-            static const double kPiece[] = MLMC_ICDF_PIECE_COEFFS;
-            static_assert(sizeof kPiece == sizeof h.piece, "piecewise table size");
-            std::memcpy(h.piece, kPiece, sizeof kPiece);
+            static const double kRows[] = MLMC_EXACT_COEFFS;
+            static_assert(sizeof kRows == sizeof(double) * kExactRows * (kExactDeg + 1), "exact table size");
+            for (int k = 0; k < kExactRows; ++k) {
+                const double* v = kRows + k * (kExactDeg + 1);
+                if (k < kDeepRows) {
+                    for (int j = 0; j < kRowLen; ++j) h.deep[k][j] = j <= kExactDeg ? v[j] : 0.0;
+                } else {  // coefficients 5 and 6 of a top cell are binary32 values (exact conversion)
+                    const int i = k - kDeepRows;
+                    h.lds.top.c01[i] = make_double2(v[0], v[1]);
+                    h.lds.top.c23[i] = make_double2(v[2], v[3]);
+                    const float hi2[2] = {(float)v[5], (float)v[6]};
+                    double packed;
+                    std::memcpy(&packed, hi2, sizeof packed);
+                    h.lds.top.c456[i] = make_double2(packed, v[4]);
+                }
+            }
             if ((e = hipMalloc(&st.exact_tab, sizeof h)) != hipSuccess) return hip_fail(e, "hipMalloc");
             if ((e = hipMemcpy(st.exact_tab, &h, sizeof h, hipMemcpyHostToDevice)) != hipSuccess)
                 return hip_fail(e, "hipMemcpy");

@@ -96,7 +96,7 @@ constexpr int kCoopSteps = 4 * kCoopProducers;            // fine steps per phas
 // barriers in every wave).  The consumer's updates and payoff terms are those of run_chunk
 // for this variant, in the same order.
 template <int RV, bool KAHAN>
-__device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const float* s_tab, const ExactTable* s_ex,
+__device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const float* s_tab, const ExactLds* s_ex,
                                double (*ring_x)[kCoopSteps][kWave], float (*ring_b)[kCoopSteps][kWave]) {
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
     const uint32_t wave = threadIdx.x / kWave;
@@ -115,11 +115,11 @@ __device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const flo
             if (f < n_phases && q < n_calls) {
                 const Words4 r = philox4x32_10(q, path, prm.ctr2, prm.pset, prm.key0, prm.key1);
                 double zx[4];
-                icdf_exact_f64x4(r.w, zx, s_ex, kc);
+                icdf_exact_f64x4(r.w, zx, &s_ex->top, deep_rows(prm), kc);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     ring_x[f & 1][base + i][lane] = zx[i];
-                    ring_b[f & 1][base + i][lane] = approx_rv<RV, DEG, float, MLMC_FP32>(r.w[i], s_tab, nullptr, s_ex->log);
+                    ring_b[f & 1][base + i][lane] = approx_rv<RV, DEG, float, MLMC_FP32>(r.w[i], s_tab, nullptr, nullptr);
                 }
             }
             __syncthreads();  // phase f written; the consumer is done with slot (f + 1) & 1
@@ -199,16 +199,16 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
     __shared__ float s_tab32[kTableRows * 4];
     __shared__ __half s_tab16[kTableRows * 4];
-    __shared__ __align__(16) unsigned char s_ex_raw[sizeof(ExactTable)];
+    __shared__ __align__(16) unsigned char s_ex_raw[sizeof(ExactCols)];
     __shared__ double ring_x[2][kCoopSteps][kWave];
     __shared__ float ring_b[2][kCoopSteps][kWave];
     __shared__ uint32_t s_pop;
-    const ExactTable* s_ex = (const ExactTable*)s_ex_raw;
+    const ExactLds* s_ex = (const ExactLds*)s_ex_raw;  // the top rows only (no learned variable here)
     for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
         s_tab32[i] = prescaled_coeff(tab32[i], i % (DEG + 1));
         s_tab16[i] = tab16[i];
     }
-    stage_exact_table(s_ex_raw, exact_tab);
+    stage_exact_table(s_ex_raw, exact_tab, sizeof(ExactCols));
     __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
     // cooperative chunks first: the block pops one, all its waves run it (block-uniform loop)

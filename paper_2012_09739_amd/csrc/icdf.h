@@ -4,12 +4,12 @@
 // Z~ = Phi~^{-1}(U) through the same uniform U; here U = (x + 1/2) 2^-32 for a word x.
 //
 // Exact (binary64): Phi^{-1}(u) = x g(w) with x = 2u - 1 and w = -log((1 - x)(1 + x)),
-// g an entire function of w.  -log is table driven (256 cells) and g is piecewise: on each
-// of 344 intervals of width 1/16 covering every w of a 32-bit word, one polynomial of
-// degree 5 in the local coordinate, its coefficients read per lane from the same table (in
-// LDS or global memory), so every lane runs the same instructions whatever its interval.
-// x is exact and y = 1 - x^2 = (1 - x)(1 + x) is rounded once (one fma); the result is
-// exactly odd under word -> 2^32 - 1 - word.
+// g an entire function of w.  w itself is never formed: G(y) = g(-log y) is piecewise
+// polynomial in y = (1 - x)(1 + x) on cells of y -- 32 per binade, chosen by the exponent
+// and the five leading mantissa bits -- of degree 6 in the offset from the cell centre, its
+// coefficients read per lane from a table (in LDS or global memory), so every lane runs
+// the same instructions whatever its cell.  x is exact and y is rounded once (one fma); the
+// result is exactly odd under word -> 2^32 - 1 - word.
 //
 // Approximate (Section 2.1, Lemmas 2.2 and 2.3): a polynomial of degree 1 or 3 in the
 // local coordinate t of one of 16 dyadic intervals of (0, 1/2] -- I_j = [2^-(j+1), 2^-j)
@@ -25,8 +25,8 @@
 
 namespace mlmc {
 
-// Cell of the table-driven log: f = R(1/c) for the cell centre c in [1/2, 1), l = -log(f)
-// rounded.
+// Cell of the table-driven log (the learned variable's input): f = R(1/c) for the cell
+// centre c in [1/2, 1), l = -log(f) rounded.
 struct LogCell {
     double f;
     double l;
@@ -39,15 +39,14 @@ constexpr int kLogCells = 256;
 // (not log c) makes the rounding of f harmless; for y in [1/2, 1) the exponent is 0 and no
 // cancellation against e ln2 occurs.  Absolute error about 1e-16 plus the rounding of the
 // result.
-__device__ __forceinline__ double neg_log_f64(double y, const LogCell* __restrict__ tab,
-                                              double p_top = 0.0, bool p_top_given = false) {
+__device__ __forceinline__ double neg_log_f64(double y, const LogCell* __restrict__ tab) {
     constexpr double kP[] = MLMC_LOG1P_COEFFS;
     const uint32_t hi = (uint32_t)__double2hiint(y);
     const double m = __builtin_amdgcn_frexp_mant(y);
     const double kd = (double)__builtin_amdgcn_frexp_exp(y);
     const LogCell c = tab[(hi >> 12) & (kLogCells - 1)];
     const double r = __builtin_fma(m, c.f, -1.0);
-    double p = p_top_given ? p_top : kP[MLMC_LOG1P_DEG];
+    double p = kP[MLMC_LOG1P_DEG];
 #pragma unroll
     for (int i = MLMC_LOG1P_DEG - 1; i >= 0; --i) p = __builtin_fma(p, r, kP[i]);
     const double log_m = c.l + __builtin_fma(r * r, p, r);
@@ -64,17 +63,41 @@ __device__ __forceinline__ double sgpr_const(double c) {
     return c;
 }
 
-// Table of the exact variable: the log cells and, interval-major, the piecewise
-// coefficients of g (piece[k][j] is coefficient j of interval k: one 48-byte row per
-// interval, read with three 16-byte loads from one address).
-constexpr int kPieces = MLMC_ICDF_PIECES;
-constexpr int kPieceDeg = MLMC_ICDF_PIECE_DEG;
-static_assert((kPieceDeg + 1) % 2 == 0, "rows of whole 16-byte pairs of coefficients");
-struct ExactTable {
-    LogCell log[kLogCells];
-    double piece[kPieces][kPieceDeg + 1];
+// Table of the exact variable: the 7 coefficients of G on each cell of y.  Cell k has the
+// key kKeyMin + k, the key of y being its biased exponent and five leading mantissa bits
+// (the upper word shifted right by 15).  The cells of y >= 2^-10 (the top cells) sit in LDS
+// as three arrays of 16-byte entries -- (c0, c1), (c2, c3) and (binary32 c5, binary32 c6,
+// c4) -- so a lane reads its cell with three 16-byte loads from one address plus fixed
+// offsets.  The deep cells below 2^-10 stay in global memory as 64-byte rows of binary64
+// coefficients and are read only by lanes whose y falls there (probability 2^-11 per word).
+constexpr int kCellBits = MLMC_EXACT_CELL_BITS;
+constexpr int kExactDeg = MLMC_EXACT_DEG;
+static_assert(kExactDeg == 6, "three 16-byte entries per top cell");
+constexpr int kRowLen = 8;
+constexpr uint32_t kKeyMin = (uint32_t)MLMC_EXACT_E_MIN << kCellBits;
+constexpr int kExactRows = MLMC_EXACT_ROWS;
+constexpr uint32_t kKeyMax = 1023u << kCellBits;  // y = 1: the constant row G(1) = g(0)
+static_assert(kKeyMin + kExactRows - 1 == kKeyMax, "one row per cell, then y = 1");
+constexpr uint32_t kKeyTop = (uint32_t)MLMC_EXACT_E_TOP << kCellBits;  // y >= 2^-10
+constexpr int kTopCells = (int)(kKeyMax + 1 - kKeyTop);
+constexpr int kDeepRows = kExactRows - kTopCells;
+
+struct ExactCols {
+    double2 c01[kTopCells];
+    double2 c23[kTopCells];
+    double2 c456[kTopCells];  // (the bits of the binary32 pair (c5, c6), c4)
 };
-static_assert(sizeof(ExactTable) % 16 == 0, "staged in 16-byte pieces");
+// what kernels stage into LDS: the top cells, then the log cells (only for the learned variable)
+struct ExactLds {
+    ExactCols top;
+    LogCell log[kLogCells];
+};
+// the device image: the LDS part, then the deep rows
+struct ExactTable {
+    ExactLds lds;
+    double deep[kDeepRows][kRowLen];
+};
+static_assert(sizeof(ExactCols) % 16 == 0 && sizeof(ExactLds) % 16 == 0, "staged in 16-byte pieces");
 
 // x = 2u - 1 = word 2^-31 + (2^-32 - 1), exact in binary64 (a multiple of 2^-32 below 1 in
 // magnitude), and y = (1 - x)(1 + x) = 1 - x^2 rounded once.
@@ -85,56 +108,77 @@ __device__ __forceinline__ double icdf_y(double x) {
     return __builtin_fma(-x, x, 1.0);
 }
 
-// g(w): interval k = floor(16 |w|) and local coordinate f = 16 |w| - k, both exact.  w is
-// below 0 only by a rounding when y rounds to 1 (|x| < 2^-26.5), where g(|w|) = g(0) to
-// far below binary64 resolution; the absolute value is a free source modifier.
-__device__ __forceinline__ double icdf_g(double w, const double (*__restrict__ piece)[kPieceDeg + 1]) {
-    const double t = __builtin_fabs(w) * (double)MLMC_ICDF_PIECE_SCALE;
-    const uint32_t k0 = (uint32_t)(int)t;
-    const uint32_t k = k0 < (uint32_t)(kPieces - 1) ? k0 : (uint32_t)(kPieces - 1);
-    const double f = __builtin_amdgcn_fract(t);
-    const double* c = piece[k];
-    double acc = c[kPieceDeg];
+// Horner's rule for the 7 coefficients of a cell at t.
+__device__ __forceinline__ double cell_poly(const double (&co)[kExactDeg + 1], double t) {
+    double acc = co[kExactDeg];
 #pragma unroll
-    for (int j = kPieceDeg - 1; j >= 0; --j) acc = __builtin_fma(acc, f, c[j]);
+    for (int j = kExactDeg - 1; j >= 0; --j) acc = __builtin_fma(acc, t, co[j]);
     return acc;
 }
 
-__device__ __forceinline__ double icdf_exact_f64(uint32_t word, const ExactTable* __restrict__ tab) {
-    const double x = icdf_x(word);
-    return x * icdf_g(neg_log_f64(icdf_y(x), tab->log), tab->piece);
+// G(y) = g(-log y) for 2^-32 < y <= 1.  c is the centre of y's cell (its key with one half
+// of the bits below), so t = y - c is exact (same binade; y = 1 reads a constant row).
+// Every lane evaluates a top cell (the deep lanes the lowest one, a finite value they
+// discard); the deep lanes then evaluate their own row from global memory.
+__device__ __forceinline__ double icdf_G(double y, const ExactCols* __restrict__ top,
+                                         const double (*__restrict__ deep)[kRowLen]) {
+    constexpr uint32_t kHalf = 1u << (19 - kCellBits);
+    uint32_t key = (uint32_t)__double2hiint(y) >> (20 - kCellBits);
+    asm volatile("" : "+v"(key));  // the deep test stays a 32-bit compare of the key
+    const double c = __hiloint2double((int)((key << (20 - kCellBits)) | kHalf), 0);
+    const double t = y - c;
+    const uint32_t k = (key > kKeyTop ? key : kKeyTop) - kKeyTop;
+    const double2 p01 = top->c01[k], p23 = top->c23[k];
+    double2 p4 = top->c456[k];
+    asm volatile("" : "+v"(p4.x), "+v"(p4.y));  // one 16-byte load, not two 8-byte ones
+    const float2 f56 = __builtin_bit_cast(float2, p4.x);
+    double g = cell_poly({p01.x, p01.y, p23.x, p23.y, p4.y, (double)f56.x, (double)f56.y}, t);
+    // g is final here for the top lanes: the deep branch below then neither merges its loads
+    // with the LDS ones (a flat load) nor shares this Horner chain through copies
+    asm volatile("" : "+v"(g));
+    if (key < kKeyTop) {
+        const double2* d = (const double2*)deep[key - kKeyMin];
+        const double2 q0 = d[0], q1 = d[1], q2 = d[2], q3 = d[3];
+        g = cell_poly({q0.x, q0.y, q1.x, q1.y, q2.x, q2.y, q3.x}, t);
+    }
+    return g;
 }
 
-// Binary64 constants held in VGPRs for a whole chunk.  Each is an operand of an fma whose
-// other constant operand is already scalar; an instruction reads at most one scalar
-// register here, so without this each use would cost a move.
+__device__ __forceinline__ double icdf_exact_f64(uint32_t word, const ExactCols* __restrict__ top,
+                                                 const double (*__restrict__ deep)[kRowLen]) {
+    const double x = icdf_x(word);
+    return x * icdf_G(icdf_y(x), top, deep);
+}
+
+// The binary64 addend 2^-32 - 1 of x = word 2^-31 + x0 held in a VGPR pair for a whole
+// chunk: the fma's other constant operand is already scalar, and an instruction reads at
+// most one scalar register here, so without this each use would cost a move.
 struct ExactConsts {
-    double x0;     // 2^-32 - 1, the addend of x = word 2^-31 + x0
-    double p_top;  // leading log1p coefficient
+    double x0;
 };
 
 __device__ __forceinline__ ExactConsts exact_consts() {
-    constexpr double kP[] = MLMC_LOG1P_COEFFS;
-    ExactConsts k{0x1p-32 - 1.0, kP[MLMC_LOG1P_DEG]};
-    asm volatile("" : "+v"(k.x0), "+v"(k.p_top));
+    ExactConsts k{0x1p-32 - 1.0};
+    asm volatile("" : "+v"(k.x0));
     return k;
 }
 
 // Exact variables of four words at once (four independent chains for the scheduler).
 __device__ __forceinline__ void icdf_exact_f64x4(const uint32_t (&word)[4], double (&z)[4],
-                                                 const ExactTable* __restrict__ tab, const ExactConsts& kc) {
-    double x[4], w[4];
+                                                 const ExactCols* __restrict__ top,
+                                                 const double (*__restrict__ deep)[kRowLen], const ExactConsts& kc) {
+    double x[4], y[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         x[k] = __builtin_fma((double)word[k], sgpr_const(0x1p-31), kc.x0);
-        w[k] = neg_log_f64(icdf_y(x[k]), tab->log, kc.p_top, true);
+        y[k] = icdf_y(x[k]);
     }
-    // one word's coefficient row at a time: each result is pinned before the next row is
-    // read (the asm takes the result as an operand and clobbers memory), so at most one
-    // row of 8 coefficients (16 VGPRs) is live instead of all of them
+    // one word's cell at a time: each result is pinned before the next cell is read (the
+    // asm takes the result as an operand and clobbers memory), so at most one cell's
+    // coefficients (14 VGPRs) are live instead of all four
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        z[k] = x[k] * icdf_g(w[k], tab->piece);
+        z[k] = x[k] * icdf_G(y[k], top, deep);
         asm volatile("" : "+v"(z[k])::"memory");
     }
 }

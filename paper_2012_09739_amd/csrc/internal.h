@@ -39,7 +39,7 @@ struct LevelParams {
     const void* table;     // 16 x (DEG + 1) coefficients (dyadic) or kPcEntries cell means, working precision
     const double* table64; // the same in binary64 (diagnostic)
     const void* mlp;       // MLP inference image (rv = MLP)
-    const void* exact_tab; // ExactTable: log cells and piecewise coefficients (exact inverse CDF)
+    const void* exact_tab; // ExactTable: rows of the exact inverse CDF, log cells
     double* partials;      // [n_chunks][kPartial] chunk partial sums
     // optional per-path outputs (device, n_paths entries each, may be null)
     double* out_pf_hat;

@@ -53,13 +53,13 @@ __global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, cons
         const uint32_t w = words[g];
         double z;
         if constexpr (RV == MLMC_RV_EXACT) {
-            z = icdf_exact_f64(w, ex);
+            z = icdf_exact_f64(w, &ex->lds.top, ex->deep);
         } else if constexpr (RV == MLMC_RV_PCONST4096) {
             if constexpr (PREC == MLMC_FP64) z = icdf_pconst_f64(w, (const double*)table);
             else if constexpr (PREC == MLMC_FP16) z = (double)__half2float(icdf_pconst_f16(w, (const __half*)table));
             else z = (double)icdf_pconst_f32(w, (const float*)table);
         } else if constexpr (RV == MLMC_RV_MLP) {
-            const float y = icdf_mlp_f32(w, (const float*)mlp, ex->log);
+            const float y = icdf_mlp_f32(w, (const float*)mlp, ex->lds.log);
             if constexpr (PREC == MLMC_FP16) z = (double)__half2float(__float2half_rn(y));
             else z = (double)y;
         } else if constexpr (PREC == MLMC_FP64) {

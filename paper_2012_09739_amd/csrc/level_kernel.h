@@ -130,11 +130,17 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Copies the exact-variable table (log cells and piecewise coefficients) into LDS.
-__device__ __forceinline__ void stage_exact_table(unsigned char* dst, const void* src) {
+// Copies the first `bytes` of the exact-variable table (the top rows, then the log cells)
+// into LDS.
+__device__ __forceinline__ void stage_exact_table(unsigned char* dst, const void* src, size_t bytes) {
     const uint4* s = (const uint4*)src;
     uint4* d = (uint4*)dst;
-    for (int i = threadIdx.x; i < (int)(sizeof(ExactTable) / 16); i += blockDim.x) d[i] = s[i];
+    for (int i = threadIdx.x; i < (int)(bytes / 16); i += blockDim.x) d[i] = s[i];
+}
+
+// The exact variable's deep rows (global memory) of a level.
+__device__ __forceinline__ const double (*deep_rows(const LevelParams& prm))[kRowLen] {
+    return ((const ExactTable*)prm.exact_tab)->deep;
 }
 
 // ---- the kernel ------------------------------------------------------------------------
@@ -161,7 +167,7 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
 // s_tab64 the binary64 one (diagnostic), both in LDS.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
 __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
-                                          const double* s_tab64, const ExactTable* s_ex) {
+                                          const double* s_tab64, const ExactLds* s_ex) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kExactOnly = (RV == MLMC_RV_EXACT);
     constexpr bool kNeedExact = kExactOnly || NESTED;
@@ -222,13 +228,13 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
         if constexpr (kNeedExact) {
             if constexpr (!SHORT) {
 #pragma unroll
-                for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], s_ex, kc);
+                for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], &s_ex->top, deep_rows(prm), kc);
             } else {
                 // levels 0 and 1 use only the first one or two words of the call
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
-                    zx[l][0] = icdf_exact_f64(r[l].w[0], s_ex);
-                    zx[l][1] = prm.n_steps > 1 ? icdf_exact_f64(r[l].w[1], s_ex) : 0.0;
+                    zx[l][0] = icdf_exact_f64(r[l].w[0], &s_ex->top, deep_rows(prm));
+                    zx[l][1] = prm.n_steps > 1 ? icdf_exact_f64(r[l].w[1], &s_ex->top, deep_rows(prm)) : 0.0;
                 }
             }
         }
@@ -378,11 +384,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == ML
     __shared__ __half s_tab16[kTab16 ? kTabN : 1];
     __shared__ double s_tab64[(kDyadic || kPconst) && DIAG ? kTabN : 1];
     __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
-    constexpr bool kNeedLog = RV == MLMC_RV_EXACT || NESTED || RV == MLMC_RV_MLP;
-    __shared__ __align__(16) unsigned char s_ex_raw[kNeedLog ? sizeof(ExactTable) : 16];
-    const ExactTable* s_ex = (const ExactTable*)s_ex_raw;
-    if constexpr (kNeedLog) {
-        stage_exact_table(s_ex_raw, prm.exact_tab);
+    // the exact variable's top rows, and the log cells for the learned variable's input
+    constexpr size_t kExBytes = RV == MLMC_RV_MLP ? sizeof(ExactLds)
+                                : (RV == MLMC_RV_EXACT || NESTED) ? sizeof(ExactCols) : 0;
+    __shared__ __align__(16) unsigned char s_ex_raw[kExBytes ? kExBytes : 16];
+    const ExactLds* s_ex = (const ExactLds*)s_ex_raw;
+    if constexpr (kExBytes > 0) {
+        stage_exact_table(s_ex_raw, prm.exact_tab, kExBytes);
         __syncthreads();
     }
     if constexpr (kDyadic) {

@@ -36,10 +36,10 @@ __global__ void pairs_kernel(uint32_t k0, uint32_t k1, uint32_t first, uint32_t 
                              float* __restrict__ xs, float* __restrict__ ts, const ExactTable* __restrict__ ex) {
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
         const uint32_t xm = pair_word(first + g, k0, k1);
-        const double r = mlp_radius(xm, ex->log);
+        const double r = mlp_radius(xm, ex->lds.log);
         if (words) words[g] = xm;
         xs[g] = (float)(r * (1.0 / 3.4) - 1.0);
-        ts[g] = (float)(icdf_exact_f64(xm, ex) + r);
+        ts[g] = (float)(icdf_exact_f64(xm, &ex->lds.top, ex->deep) + r);
     }
 }
 
