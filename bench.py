@@ -51,8 +51,8 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 ALG_OPS_PER_STEP = 42.0
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (215.9375 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "d3a1289afa8c8f270fbb8139d780141be7ae2460cd2d196a25c6636c38c9571b"
+TRAFFIC_BYTES_PER_LAUNCH = (210.9375 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
+TRAFFIC_SOURCES_SHA256 = "c5b4890eec6d0c5722ee4b243a6f37e4c2a5120d381d63d7b5dea304465fc265"
 KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
                   "icdf_exact_coeffs.h")
 

@@ -240,7 +240,10 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            if (4 * q + i >= prm.n_steps) break;  // only at levels 0 and 1
+            // only levels 0 and 1 stop inside a call; the instances with the exact variable
+            // run them as SHORT ones, so their other instance never checks
+            if constexpr (SHORT || !kNeedExact)
+                if (4 * q + i >= prm.n_steps) break;
             const bool coarse = (i & 1) != 0;
             if constexpr (kNeedExact) {
 #pragma unroll
