@@ -48,9 +48,13 @@ template <int RV, int PREC>
 __global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, const void* table,
                             const void* mlp, const ExactTable* __restrict__ ex, double* __restrict__ out) {
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
-         g += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t w = words[g];
+    // whole wavefronts step together (the learned variable uses matrix instructions): lanes
+    // past the end evaluate word 0 and store nothing
+    const uint64_t lane = threadIdx.x & (kWave - 1);
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; base < n;
+         base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t g = base + lane;
+        const uint32_t w = g < n ? words[g] : 0u;
         double z;
         if constexpr (RV == MLMC_RV_EXACT) {
             z = icdf_exact_f64(w, &ex->lds.top, ex->deep);
@@ -71,7 +75,7 @@ __global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, cons
         } else {
             z = (double)__half2float(icdf_dyadic_f16<DEG>(w, (const __half*)table));
         }
-        out[g] = z;
+        if (g < n) out[g] = z;
     }
 }
 

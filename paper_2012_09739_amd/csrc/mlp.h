@@ -6,8 +6,9 @@
 //   h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = W3 . h2 + b3,
 //   Z~ = y - r (u < 1/2), r - y (u >= 1/2);
 // y learns the smooth residual Phi^{-1}(u') + r.  Inference uses the parameters rounded to
-// binary16 (staged in LDS widened to binary32) with binary32 arithmetic and accumulation;
-// r comes from the binary64 -log so that it stays accurate next to u' = 1/2.
+// binary16 (staged in LDS widened to binary32) with binary32 arithmetic and accumulation, the
+// 16 x 16 layer as binary32 matrix instructions; r comes from the binary64 -log so that it
+// stays accurate next to u' = 1/2.
 #pragma once
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -36,32 +37,62 @@ __device__ __forceinline__ double mlp_radius(uint32_t xm, const LogCell* __restr
     return __builtin_sqrt(2.0 * neg_log_f64(two_u, logtab));
 }
 
-// Network output for input x; W is the binary32 image of the binary16 parameters (LDS).
-// The empty asm with a memory clobber keeps the weight reads inside the call site, so the
-// 321 weights are read from LDS (uniform broadcast) instead of being hoisted into VGPRs.
-__device__ __forceinline__ float mlp_eval(float x, const float* __restrict__ W) {
-    asm volatile("" ::: "memory");
-    float h1[kMlpHidden];
+// Network output for every lane's own input x, the 16 x 16 layer on the matrix cores.  W is
+// the binary32 image of the binary16 parameters (LDS or global memory).  All 64 lanes of
+// the wavefront must call it together (a matrix instruction works on the whole wave).
+//
+// Lanes are split as lane = 16 g + c.  For the samples of lanes 16 b + c (b = 0..3), lane
+// 16 g + c evaluates the hidden units 4 j + g of the first layer, which is the B operand of
+// v_mfma_f32_16x16x4_f32 (B[k][s] in lane 16 k + s) with A[n][k] = W2[n][4 j + k] (A[n][k]
+// in lane 16 k + n): four such products over j give out[n][s] for one block of 16 samples,
+// returned as D[n][s] = d[n % 4] in lane 16 (n / 4) + s.  Each lane then applies the second
+// tanh and the output weights to its four units n = 4 g .. 4 g + 3 of every block, the
+// partial sums are added over the four lane groups, and lane 16 g + c keeps block g: its own
+// sample.  The products and sums are binary32, as in the per-lane evaluation.
+__device__ __forceinline__ float mlp_eval_wave(float x, const float* __restrict__ W) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t c = lane & 15u, g = lane >> 4;
+    float w1[4], b1[4], w2[4];
 #pragma unroll
-    for (int k = 0; k < kMlpHidden; ++k) h1[k] = tanh_fast(__builtin_fmaf(W[kW1 + k], x, W[kB1 + k]));
-    float y = W[kB3];
-#pragma unroll
-    for (int k = 0; k < kMlpHidden; ++k) {
-        asm volatile("" ::: "memory");
-        float a = W[kB2 + k];
-#pragma unroll
-        for (int j = 0; j < kMlpHidden; ++j) a = __builtin_fmaf(W[kW2 + k * kMlpHidden + j], h1[j], a);
-        y = __builtin_fmaf(W[kW3 + k], tanh_fast(a), y);
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t k = 4u * j + g;
+        w1[j] = W[kW1 + k];
+        b1[j] = W[kB1 + k];
+        w2[j] = W[kW2 + c * kMlpHidden + k];
     }
-    return y;
+    float part[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float xb = __shfl(x, 16 * b + (int)c, kWave);
+        v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(w2[j], tanh_fast(__builtin_fmaf(w1[j], xb, b1[j])), d, 0, 0, 0);
+        float p = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t n = 4u * g + r;
+            p = __builtin_fmaf(W[kW3 + n], tanh_fast(d[r] + W[kB2 + n]), p);
+        }
+        part[b] = p;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        part[b] += __shfl_xor(part[b], 16, kWave);
+        part[b] += __shfl_xor(part[b], 32, kWave);
+    }
+    const float y = g == 0 ? part[0] : g == 1 ? part[1] : g == 2 ? part[2] : part[3];
+    return y + W[kB3];
 }
 
+// The learned approximate variable of every lane's word (all 64 lanes together).
 __device__ __forceinline__ float icdf_mlp_f32(uint32_t word, const float* __restrict__ W,
                                               const LogCell* __restrict__ logtab) {
     const uint32_t xm = word ^ (uint32_t)((int32_t)word >> 31);  // ~word on the upper half
     const double r = mlp_radius(xm, logtab);
     const float x = (float)(r * (1.0 / 3.4) - 1.0);
-    const float q = mlp_eval(x, W) - (float)r;
+    const float q = mlp_eval_wave(x, W) - (float)r;
     return apply_sign(q, word & 0x80000000u);
 }
 
