@@ -126,7 +126,7 @@ struct DevState {
     size_t scratch_bytes = 0;
     double* out8 = nullptr;             // result slot of the synchronous entry point
     float* mlp = nullptr;               // MLP inference image (binary16 values as binary32)
-    void* exact_tab = nullptr;          // ExactTable: rows of the exact variable, log cells
+    void* exact_tab = nullptr;          // ExactTable: cells of the exact variable, log cells
     bool mlp_loaded = false;
     // level sets: their own streams, events (two per call and two per set) and device memory
     // (result slots, then one workspace per call), created on first use

@@ -130,7 +130,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Copies the first `bytes` of the exact-variable table (the top rows, then the log cells)
+// Copies the first `bytes` of the exact-variable table (the top cells, then the log cells)
 // into LDS.
 __device__ __forceinline__ void stage_exact_table(unsigned char* dst, const void* src, size_t bytes) {
     const uint4* s = (const uint4*)src;
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == ML
     __shared__ __half s_tab16[kTab16 ? kTabN : 1];
     __shared__ double s_tab64[(kDyadic || kPconst) && DIAG ? kTabN : 1];
     __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
-    // the exact variable's top rows, and the log cells for the learned variable's input
+    // the exact variable's top cells, and the log cells for the learned variable's input
     constexpr size_t kExBytes = RV == MLMC_RV_MLP ? sizeof(ExactLds)
                                 : (RV == MLMC_RV_EXACT || NESTED) ? sizeof(ExactCols) : 0;
     __shared__ __align__(16) unsigned char s_ex_raw[kExBytes ? kExBytes : 16];
