@@ -95,7 +95,7 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernel; "
+        print("bench.py runs on one GPU only: it measures the single-GPU kernel; "
               "paths shard across GPUs by path_offset but no multi-GPU run is made",
               file=sys.stderr)
         sys.exit(2)
