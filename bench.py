@@ -52,9 +52,9 @@ ALG_OPS_PER_STEP = 42.0
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
 TRAFFIC_BYTES_PER_LAUNCH = (210.9375 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "981b7d95085caba48d060ff66fcdbb31db8ae9238c56ba233d9ba399104afab9"
+TRAFFIC_SOURCES_SHA256 = "d22d7bed81db7971a6a06449ff72bc16ddbed1d2ccb6b80446af26d221ac7542"
 KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
-                  "icdf_exact_coeffs.h")
+                  "icdf_exact_coeffs.h", "abi.cpp")  # abi.cpp: the launch grid
 
 
 def kernel_sources_sha256():

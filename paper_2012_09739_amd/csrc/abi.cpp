@@ -369,12 +369,19 @@ LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevS
     return p;
 }
 
+// Four-wave blocks, one chunk per wave up to 32 blocks per CU (several times what is resident
+// at once), past that an equal number of chunks per wave.  With more blocks than fit, the
+// dispatcher hands the last chunks to whichever CU frees first, so the tail of the launch
+// stays busy; a grid of only the resident waves, two chunks each, left it to a few CUs.
 void launch_shape(const DevState& st, uint64_t n_chunks, int* grid, int* block) {
     const int waves_per_block = 4;
     *block = waves_per_block * kWave;
-    const uint64_t max_blocks = (uint64_t)st.n_cu * 8;  // 32 resident waves per CU
+    const uint64_t max_blocks = (uint64_t)st.n_cu * 32;
     uint64_t blocks = (n_chunks + waves_per_block - 1) / waves_per_block;
-    if (blocks > max_blocks) blocks = max_blocks;
+    if (blocks > max_blocks) {  // ceil(blocks / rounds) <= max_blocks
+        const uint64_t rounds = (blocks + max_blocks - 1) / max_blocks;
+        blocks = (blocks + rounds - 1) / rounds;
+    }
     if (blocks == 0) blocks = 1;
     *grid = (int)blocks;
 }
