@@ -32,11 +32,15 @@ sys.path.insert(0, ROOT)
 LEVELS = list(range(11))
 N_PATHS = 2 ** 20
 SEED = 0
-# VALU issue peak of MI355X in binary64-equivalent lane-operations: 256 CUs x 64 lanes x
-# 2.4 GHz (= the binary64 vector peak 78.6 TFLOP/s / 2 flops per FMA).  32-bit operations
-# (binary32, integer, logic) issue at twice that rate (the binary32 vector peak 157.3 TFLOP/s)
-# and weigh 1/2; the 32x32->64 integer product (v_mad_u64_u32) weighs 2 (measured).
+# VALU issue peak of MI355X in binary64-equivalent lane-operations ("slots"): 256 CUs x 64
+# lanes x 2.4 GHz (= the binary64 vector peak 78.6 TFLOP/s / 2 flops per FMA).  The weight of
+# an opcode is its issue cost relative to v_fma_f64, from the issue-rate probes
+# (libvalurates.so, bench leg "valu_rates"): 32-bit operations (binary32, integer, logic)
+# issue at twice the binary64 rate and weigh 1/2 (the binary32 vector peak 157.3 TFLOP/s).
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+# vector peaks of MI355X (TFLOP/s): binary64 and binary32 published; packed binary16 at the
+# rate the probes measure for v_pk_fma_f16 (two FMAs per lane per instruction)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "f16": 157.3}
 # algorithmic binary64-equivalent VALU lane-operations per coupled path-step of the nested
 # binary32 piecewise-linear kernel with Kahan updates, for the minimal operation sequence of
 # this formulation:
@@ -49,12 +53,29 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 #   piecewise-linear inverse CDF, binary32: 13 32-bit operations x 1/2             6.5
 #   binary32 fine and half coarse Kahan EM update: (8 + 9/2) x 1/2                 6.25
 ALG_OPS_PER_STEP = 42.0
+# the dominant kernels, each timed alone: HIP events on the launching stream around
+# mlmc_paths with no per-path outputs, which launches exactly the level kernel of
+# mlmc_level_ex (same instance and grid) without the two kernels of the chunk reduction
+ROOFLINE_KERNELS = {
+    "fp32": dict(precision="MLMC_FP32", mode="MLMC_NESTED_PWL16", kahan=1, level=10, n_paths=2 ** 20,
+                 alg_ops=ALG_OPS_PER_STEP,
+                 kernel="level_kernel<FP32, PWL16, nested, Kahan> at level 10 (2^20 paths x 1024 steps)"),
+    "fp16": dict(precision="MLMC_FP16", mode="MLMC_NESTED_CUBIC16", kahan=1, level=6, n_paths=2 ** 24,
+                 alg_ops=None,
+                 kernel="level_kernel<FP16, CUBIC16, nested, Kahan> at level 6 (2^24 paths x 64 steps)"),
+}
+# floating-point operations per launch of each kernel by precision, from rocprofv3's
+# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F16,F32,F64} counters (64 lanes x (ADD + MUL + TRANS +
+# 2 FMA) per wave instruction; a packed binary16 instruction counts twice), valid for the
+# kernel sources hashed below (None: not taken for these sources)
+FLOPS_PER_LAUNCH = {"fp32": None, "fp16": None}
+FLOPS_SOURCES_SHA256 = None
 # HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
 TRAFFIC_BYTES_PER_LAUNCH = (210.9375 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
 TRAFFIC_SOURCES_SHA256 = "d22d7bed81db7971a6a06449ff72bc16ddbed1d2ccb6b80446af26d221ac7542"
 KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
-                  "icdf_exact_coeffs.h", "abi.cpp")  # abi.cpp: the launch grid
+                  "level_f16.hip", "icdf_exact_coeffs.h", "abi.cpp")  # abi.cpp: the launch grid
 
 
 def kernel_sources_sha256():
@@ -73,7 +94,12 @@ def traffic_bytes():
     return TRAFFIC_BYTES_PER_LAUNCH
 
 
-REPORT_LEGS = ("plain", "fp16", "batch", "mlp", "sweep", "adaptive", "milstein", "pconst")
+REPORT_LEGS = ("plain", "fp16", "batch", "mlp", "sweep", "adaptive", "milstein", "pconst", "valu_rates")
+# opcodes of the issue-rate probes (include/valu_rates.h order)
+VALU_OPS = ("v_fma_f64", "v_mul_f64", "v_add_f64", "v_fma_f32", "v_mul_f32", "v_pk_fma_f16", "v_pk_mul_f16",
+            "v_fma_f16", "v_bitop3_b32 (xor3)", "v_add_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_ffbh_u32",
+            "v_exp_f32", "v_rcp_f32", "v_med3_f32", "v_mad_u64_u32", "v_cvt_f32_f64 + v_cvt_f64_f32",
+            "v_cvt_f16_f32 + v_cvt_f32_f16")
 
 
 def parse():
@@ -117,7 +143,7 @@ def main():
     ws_bytes = max(M.mlmc_level_workspace_bytes(x) for x in args[0])
     ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device="cuda")
     top = LEVELS[-1]
-    ev = []   # (start, end) events around the dominant kernel: level 10, Kahan
+    ev = []   # (start, end) events around the dominant call: level 10, Kahan (kernel + reduction)
 
     def step(record):
         for k in (0, 1):
@@ -142,10 +168,12 @@ def main():
     steps_per_pass = 2 * N_PATHS * sum(2 ** l for l in LEVELS)
     seconds = t1 - t0
     value = a.steps * steps_per_pass / seconds
-    kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
-    achieved = ALG_OPS_PER_STEP * N_PATHS * 2 ** top / (kern_ms * 1e-3) / 1e12
+    launch_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
     sums = out.cpu().numpy()
     assert all(math.isfinite(v) for v in sums.ravel()), "non-finite level sums"
+
+    roof = {k: roofline_block(M, torch, k) for k in ROOFLINE_KERNELS}
+    roof["fp32"]["call_ms_with_reduction"] = launch_ms
 
     extra = {}
     if not a.no_speedup:
@@ -186,15 +214,61 @@ def main():
                                "Kahan off and on",
                    "levels": LEVELS, "paths_per_level": N_PATHS, "kahan": [0, 1],
                    "coupled_path_steps_per_step": steps_per_pass, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS,
-                     "unit": "T binary64-equivalent VALU lane-ops/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": traffic_bytes(),
-                     "kernel": "level_kernel<FP32, PWL16, nested, kahan> at level 10 (2^20 paths x 1024 steps)",
-                     "kernel_ms": kern_ms, "alg_ops_per_path_step": ALG_OPS_PER_STEP},
+        "roofline": roof["fp32"],
+        "roofline_fp16": roof["fp16"],
         "cpu_baseline": cpu,
     }
     line.update(extra)
     print(json.dumps(line), flush=True)
+
+
+def kernel_ms(M, torch, args, reps=10, warm=2):
+    """HIP-event times (ms) of the level kernel alone on the current stream: mlmc_paths with no
+    per-path outputs launches the level kernel of mlmc_level_ex and nothing else."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warm):
+        M.mlmc_paths(args, stream=stream)
+    evs = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        M.mlmc_paths(args, stream=stream)
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in evs]
+
+
+def roofline_block(M, torch, key):
+    """Issue roofline of one dominant kernel (alu bound): algorithmic binary64-equivalent VALU
+    slots per launch over its measured duration against the 39.32 T slots/s peak, with the
+    counter-derived FLOP/s of each precision against its vector peak."""
+    k = ROOFLINE_KERNELS[key]
+    call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
+    args = M.level_args(call, k["level"], k["n_paths"], getattr(M, k["precision"]), getattr(M, k["mode"]),
+                        k["kahan"], SEED)
+    times = kernel_ms(M, torch, args)
+    ms = sum(times) / len(times)
+    steps = k["n_paths"] << k["level"]
+    blk = {"bound": "alu", "peak": PEAK_VALU_TOPS, "unit": "T binary64-equivalent VALU lane-ops/s",
+           "kernel": k["kernel"], "kernel_ms": ms, "kernel_ms_min": min(times), "launches_timed": len(times),
+           "coupled_path_steps_per_s": steps / (ms * 1e-3), "alg_ops_per_path_step": k["alg_ops"],
+           "traffic": traffic_bytes() if key == "fp32" else None}
+    if k["alg_ops"] is not None:
+        achieved = k["alg_ops"] * steps / (ms * 1e-3) / 1e12
+        blk.update(achieved=achieved, frac=achieved / PEAK_VALU_TOPS)
+    else:
+        blk.update(achieved=None, frac=None)
+    fl = FLOPS_PER_LAUNCH.get(key)
+    if fl is not None and FLOPS_SOURCES_SHA256 == kernel_sources_sha256():
+        per = {p: {"tflops": fl[p] / (ms * 1e-3) / 1e12, "peak_tflops": PEAK_TFLOPS[p],
+                   "frac": fl[p] / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[p]} for p in fl}
+        blk["flops"] = per
+        # the VALU time the floating-point work alone would take at each precision's peak
+        blk["flop_time_frac"] = sum(v["frac"] for v in per.values())
+    else:
+        blk["flops"] = None
+    return blk
 
 
 def equal_variance_report(M, E, call):
@@ -457,8 +531,33 @@ def reports(M, E, torch, legs=REPORT_LEGS):
                            var(plain_rows, 0), cost(plain_rows), var(a_rows, 0), cost(a_rows), var(n_rows, 1),
                            cost(n_rows))}
         rep["pconst4096_vs_dyadic_call_levels0to10_2p20"] = pc
+    if "valu_rates" in legs:
+        rep["valu_issue_rates"] = valu_rates()
     np.seterr(all="ignore")
     return rep
+
+
+def valu_rates(waves=(8, 4), iters=4096):
+    """Lane-instructions per CU per ns of single VALU opcodes (libvalurates.so), per resident
+    wavefronts per SIMD; divided by the shader clock of the launch (GHz) they are per clock."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2012_09739_amd", "libvalurates.so")
+    if not os.path.exists(path):
+        raise RuntimeError("libvalurates.so is not built: run python -m paper_2012_09739_amd.build")
+    lib = ctypes.CDLL(path)
+    lib.valu_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    for w in waves:
+        row = {}
+        for op, name in enumerate(VALU_OPS):
+            r, ms = ctypes.c_double(), ctypes.c_double()
+            rc = lib.valu_rate(op, w, iters, ctypes.byref(r), ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError("valu_rate(%s) failed: %d" % (name, rc))
+            row[name] = {"lane_instr_per_cu_per_ns": r.value, "kernel_ms": ms.value}
+        out["waves_per_simd_%d" % w] = row
+    return out
 
 
 CPU_SINGLE_PATHS = 2 ** 15     # paths per level, one process

@@ -1,4 +1,5 @@
-"""Builds libmlmc.so (the HIP kernels and the C-ABI) for gfx950, in-tree.
+"""Builds libmlmc.so (the HIP kernels and the C-ABI) and libvalurates.so (the VALU issue-rate
+probes behind the issue roofline) for gfx950, in-tree.
 
     python -m paper_2012_09739_amd.build        (or build() from Python)
 
@@ -17,6 +18,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlmc.so")
+# issue rates of single VALU opcodes (the weights of the level kernels' issue roofline):
+# a separate library, not part of the method's C-ABI
+RATES_SOURCE = "valu_rates.hip"
+RATES_LIB = os.path.join(HERE, "libvalurates.so")
 
 HIP_SOURCES = ["level_f64.hip", "level_f32.hip", "level_f16.hip", "level_bf16.hip",
                "level_milstein_f64.hip", "level_milstein_f32.hip", "level_milstein_f16.hip",
@@ -60,9 +65,12 @@ def build(verbose=False, jobs=None):
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         cmds.append(["g++", "-c", *COMMON, os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    rates_tmp = RATES_LIB + ".tmp"
+    cmds.append([hipcc, "-shared", *COMMON, *HIP_FLAGS, os.path.join(CSRC, RATES_SOURCE), "-o", rates_tmp])
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for f in [ex.submit(_run, c, verbose) for c in cmds]:
             f.result()
+    os.replace(rates_tmp, RATES_LIB)
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)

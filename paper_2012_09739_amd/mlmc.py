@@ -7,7 +7,6 @@ The library must have been built (paper_2012_09739_amd.build); there is no fallb
 """
 
 import ctypes
-import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -312,9 +311,3 @@ def mlmc_mlp_load(d_params, stream=None):
 def mlmc_last_error():
     return lib().mlmc_last_error().decode()
 
-
-def mean_var(total, total_sq, m):
-    """Sample mean and unbiased variance from a sum and a sum of squares."""
-    mean = total / m
-    var = (total_sq - total * total / m) / (m - 1) if m > 1 else math.nan
-    return mean, var

@@ -15,6 +15,7 @@ from oracle import fp, icdf, mlmc, philox
 from test_gpu_parity import close, sums_close
 
 import paper_2012_09739_amd as M
+from paper_2012_09739_amd import estimators as E
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +58,7 @@ def test_bf16_level_sums_and_rounding_bound():
     M.mlmc_level_ex(args, out)
     torch.cuda.synchronize()
     s = out.cpu().numpy()
-    var = M.mean_var(s[3], s[7], 1 << 16)[1]
+    var = E.level_stats(s[3], s[7], 1 << 16)[1]
     N, rho = 2 ** level, fp.UNIT_ROUNDOFF[fp.BF16]
     bound = N * rho * rho * (1 + 0.05 / N) ** (2 * N) * math.exp(0.04) * math.exp(2 * 0.05 + 0.04)
     assert 0 < var <= bound

@@ -78,4 +78,5 @@ def test_full_size_sampled_paths_level10():
                          seed=0, stream=1)
     np.testing.assert_array_equal(g["pf_bar"][idx], o["Pf_bar"])
     np.testing.assert_array_equal(g["pc_bar"][idx], o["Pc_bar"])
-    assert np.all(close(g["pf_hat"][idx], o["Pf_hat"], 1e-12))
+    assert np.all(close(g["pf_hat"][idx], o["Pf_hat"], 1e-13))
+    assert np.all(close(g["pc_hat"][idx], o["Pc_hat"], 1e-13))
