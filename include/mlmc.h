@@ -188,6 +188,18 @@ int mlmc_level_set_run(const mlmc_level_args_t* args, int n_calls, mlmc_result_t
 int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspace,
                   size_t workspace_bytes, void* hip_stream);
 
+/* mlmc_level_ex for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same fixed-order reduction (so the same bits), with the chunk partials and stage rows in a
+ * library-owned device array of 4 MiB (room for 65536 chunks: n_paths <= 2^22, or 2^23 in
+ * MLMC_FP16) that each device holds from library load until the process ends.  The call
+ * allocates and frees nothing: the current device must have been set up by mlmc_init first
+ * (else MLMC_EUNSUPPORTED).  args: host; d_out: device, 8 doubles (sum[0..3], sumsq[0..3]),
+ * written when hip_stream reaches the call.  Larger n_paths: MLMC_EINVAL (checked before any
+ * HIP call).  Every call on one device shares that device's array and writes every entry it
+ * reads, so nothing carries over between calls; calls that overlap on one device race. */
+int mlmc_level_noalloc(const mlmc_level_args_t* args, double* d_out, void* hip_stream);
+
 /* Bytes of device scratch one mlmc_level_ex call needs (0 on invalid arguments). */
 size_t mlmc_level_workspace_bytes(const mlmc_level_args_t* args);
 

@@ -110,6 +110,17 @@ double rounded_to(int precision, double c) {
     return c;
 }
 
+// ---- device scratch of mlmc_level_noalloc --------------------------------------------------
+// The chunk partials and stage rows of one level call, for callers that cannot allocate: a
+// file-scope device array (each device holds its own copy from the time the code object is
+// loaded until the process ends).  Host code never passes `scratch` itself to a kernel (on the
+// host the name is a stand-in, not a device address); device_state() looks up each device's
+// address once with hipGetSymbolAddress and keeps it in DevState::noalloc_scratch.
+constexpr uint64_t kNoAllocMaxChunks = 65536;  // 2^22 paths in binary32/64, 2^23 in binary16
+constexpr size_t kNoAllocBytes = (size_t)(kNoAllocMaxChunks + kStageRowsMax) * kPartial * sizeof(double) + 64;
+static_assert(kNoAllocBytes % 8 == 0, "scratch holds doubles");
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
 // ---- per-device state -------------------------------------------------------------------
 constexpr int kSetStreams = 4;     // streams of a level set (the hardware queues of a process)
 constexpr int kMaxSetCalls = 4096;  // calls per level set
@@ -124,6 +135,7 @@ struct DevState {
     void* pconst[4] = {nullptr};       // [precision], kPcEntries cell means
     double* scratch = nullptr;
     size_t scratch_bytes = 0;
+    double* noalloc_scratch = nullptr;  // this device's address of `scratch`
     double* out8 = nullptr;             // result slot of the synchronous entry point
     float* mlp = nullptr;               // MLP inference image (binary16 values as binary32)
     void* exact_tab = nullptr;          // ExactTable: cells of the exact variable, log cells
@@ -219,6 +231,8 @@ int device_state(DevState** out) {
         if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
             return fail(MLMC_ENODEV, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
         st.n_cu = prop.multiProcessorCount;
+        if ((e = hipGetSymbolAddress((void**)&st.noalloc_scratch, HIP_SYMBOL(scratch))) != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
         if ((e = hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
         if ((e = hipEventCreate(&st.ev0)) != hipSuccess || (e = hipEventCreate(&st.ev1)) != hipSuccess)
             return hip_fail(e, "hipEventCreate");
@@ -556,6 +570,32 @@ int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspac
         partials = st->scratch;
     }
     return enqueue_level(*st, args, v, d_out, partials, nullptr, nullptr, nullptr, nullptr, nullptr,
+                         (hipStream_t)hip_stream);
+}
+
+int mlmc_level_noalloc(const mlmc_level_args_t* args, double* d_out, void* hip_stream) {
+    Variant v;
+    int rc = validate_args(args, &v);
+    if (rc) return rc;
+    if (!d_out) return fail(MLMC_EINVAL, "d_out is NULL");
+    const uint64_t n_chunks = n_chunks_of(args);
+    if (n_chunks > kNoAllocMaxChunks)
+        return fail(MLMC_EINVAL,
+                    "n_paths %llu needs %llu chunks; mlmc_level_noalloc holds at most %llu (2^22 paths, 2^23 in "
+                    "binary16)",
+                    (unsigned long long)args->n_paths, (unsigned long long)n_chunks,
+                    (unsigned long long)kNoAllocMaxChunks);
+    int dev = 0;
+    if ((rc = current_device(&dev))) return rc;
+    DevState* st = nullptr;
+    {
+        // look the device up without creating it: set-up allocates, this entry point does not
+        std::lock_guard<std::mutex> lock(g_mutex);
+        auto it = g_devs.find(dev);
+        if (it != g_devs.end() && it->second.ready) st = &it->second;
+    }
+    if (!st) return fail(MLMC_EUNSUPPORTED, "mlmc_level_noalloc allocates nothing: call mlmc_init(%d) first", dev);
+    return enqueue_level(*st, args, v, d_out, st->noalloc_scratch, nullptr, nullptr, nullptr, nullptr, nullptr,
                          (hipStream_t)hip_stream);
 }
 

@@ -78,6 +78,7 @@ _SIGNATURES = {
     "mlmc_level_set_run": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), ctypes.c_int,
                                           ctypes.POINTER(mlmc_result_t), ctypes.POINTER(ctypes.c_double)]),
     "mlmc_level_ex": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), _P, _P, ctypes.c_size_t, _P]),
+    "mlmc_level_noalloc": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), _P, _P]),
     "mlmc_level_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(mlmc_level_args_t)]),
     "mlmc_paths": (ctypes.c_int, [ctypes.POINTER(mlmc_level_args_t), _P, _P, _P, _P, _P, _P]),
     "mlmc_uniforms": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32,
@@ -208,6 +209,11 @@ def mlmc_level_ex(args, d_out, workspace=None, workspace_bytes=0, stream=None):
         workspace_bytes = workspace.numel() * workspace.element_size()
     _check(lib().mlmc_level_ex(ctypes.byref(args), _ptr(d_out), _ptr(workspace), workspace_bytes,
                                _stream(stream)))
+
+
+def mlmc_level_noalloc(args, d_out, stream=None):
+    """mlmc_level_ex with the library's fixed device scratch (allocates nothing; needs mlmc_init)."""
+    _check(lib().mlmc_level_noalloc(ctypes.byref(args), _ptr(d_out), _stream(stream)))
 
 
 def mlmc_paths(args, pf_hat=None, pc_hat=None, pf_bar=None, pc_bar=None, xf_tilde=None, stream=None):

@@ -83,6 +83,19 @@ def test_null_pointers_rejected():
     assert lib.mlmc_level_ex(None, None, None, 0, None) == M.MLMC_EINVAL
     assert lib.mlmc_table(1, 0, None) == M.MLMC_EINVAL
     assert lib.mlmc_level_workspace_bytes(None) == 0
+    assert lib.mlmc_level_noalloc(ctypes.byref(args), None, None) == M.MLMC_EINVAL
+    assert lib.mlmc_level_noalloc(None, None, None) == M.MLMC_EINVAL
+
+
+@pytest.mark.parametrize("prec,n", [(M.MLMC_FP32, (1 << 22) + 1), (M.MLMC_FP64, 1 << 23),
+                                    (M.MLMC_FP16, (1 << 23) + 1)])
+def test_noalloc_size_limit_before_device(prec, n):
+    # the fixed scratch holds 65536 chunks: 2^22 paths (2^23 in binary16); checked before any HIP call
+    args = M.level_args(M.gbm(), 3, n, prec, M.MLMC_NESTED_PWL16)
+    with pytest.raises(M.MlmcError) as e:
+        M.mlmc_level_noalloc(args, 1 << 20, stream=0)
+    assert e.value.code == M.MLMC_EINVAL
+    assert "65536" in M.mlmc_last_error()
 
 
 def test_workspace_size():
