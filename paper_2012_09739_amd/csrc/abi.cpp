@@ -365,6 +365,8 @@ uint64_t n_chunks_of(const mlmc_level_args_t* a) {
     return (a->n_paths + cp - 1) / cp;
 }
 
+uint64_t n_rows_of(const mlmc_level_args_t* a) { return rows_of(n_chunks_of(a), a->level); }
+
 LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevState& st, double* partials) {
     LevelParams p;
     fill_level_params(&p, a->sde, a->level, a->precision, a->n_paths, a->path_offset, a->seed, a->stream, a->pset);
@@ -383,15 +385,15 @@ LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevS
     return p;
 }
 
-// Four-wave blocks, one chunk per wave up to 32 blocks per CU (several times what is resident
-// at once), past that an equal number of chunks per wave.  With more blocks than fit, the
-// dispatcher hands the last chunks to whichever CU frees first, so the tail of the launch
-// stays busy; a grid of only the resident waves, two chunks each, left it to a few CUs.
-void launch_shape(const DevState& st, uint64_t n_chunks, int* grid, int* block) {
+// Four-wave blocks, one partial row per wave up to 32 blocks per CU (several times what is
+// resident at once), past that an equal number of rows per wave.  With more blocks than fit,
+// the dispatcher hands the last rows to whichever CU frees first, so the tail of the launch
+// stays busy; a grid of only the resident waves, two rows each, left it to a few CUs.
+void launch_shape(const DevState& st, uint64_t n_rows, int* grid, int* block) {
     const int waves_per_block = 4;
     *block = waves_per_block * kWave;
     const uint64_t max_blocks = (uint64_t)st.n_cu * 32;
-    uint64_t blocks = (n_chunks + waves_per_block - 1) / waves_per_block;
+    uint64_t blocks = (n_rows + waves_per_block - 1) / waves_per_block;
     if (blocks > max_blocks) {  // ceil(blocks / rounds) <= max_blocks
         const uint64_t rounds = (blocks + max_blocks - 1) / max_blocks;
         blocks = (blocks + rounds - 1) / rounds;
@@ -406,7 +408,7 @@ int enqueue_level(DevState& st, const mlmc_level_args_t* a, const Variant& v, do
                   double* out_xf_tilde, hipStream_t s) {
     if (v.rv == MLMC_RV_MLP && !st.mlp_loaded)
         return fail(MLMC_EUNSUPPORTED, "MLMC_RV_MLP needs weights: call mlmc_mlp_load first");
-    const uint64_t n_chunks = n_chunks_of(a);
+    const uint64_t n_rows = n_rows_of(a);
     LevelParams p = make_params(a, v, st, partials);
     p.out_pf_hat = out_pf_hat;
     p.out_pc_hat = out_pc_hat;
@@ -414,16 +416,16 @@ int enqueue_level(DevState& st, const mlmc_level_args_t* a, const Variant& v, do
     p.out_pc_bar = out_pc_bar;
     p.out_xf_tilde = out_xf_tilde;
     hipError_t e;
-    // layout of the workspace: chunk partials, then the stage rows
-    double* stage = partials + (n_chunks == 0 ? 1 : n_chunks) * kPartial;
+    // layout of the workspace: partial rows, then the stage rows
+    double* stage = partials + (n_rows == 0 ? 1 : n_rows) * kPartial;
     int grid, block;
-    launch_shape(st, n_chunks, &grid, &block);
-    if (n_chunks > 0) {
+    launch_shape(st, n_rows, &grid, &block);
+    if (n_rows > 0) {
         e = launch_level(v, p, grid, block, s);
         if (e != hipSuccess) return hip_fail(e, "level kernel launch");
     }
-    if (d_out) {  // with no chunks the first stage reads no row and the sums are zero
-        e = launch_reduce(partials, n_chunks, stage, d_out, s);
+    if (d_out) {  // with no rows the first stage reads no row and the sums are zero
+        e = launch_reduce(partials, n_rows, stage, d_out, s);
         if (e != hipSuccess) return hip_fail(e, "reduction kernel launch");
     }
     return MLMC_OK;
@@ -550,7 +552,7 @@ const char* mlmc_last_error(void) { return g_error.c_str(); }
 size_t mlmc_level_workspace_bytes(const mlmc_level_args_t* args) {
     Variant v;
     if (validate_args(args, &v)) return 0;
-    return level_workspace_bytes(n_chunks_of(args));
+    return level_workspace_bytes(n_rows_of(args));
 }
 
 int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspace, size_t workspace_bytes,
@@ -559,7 +561,7 @@ int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspac
     int rc = validate_args(args, &v);
     if (rc) return rc;
     if (!d_out) return fail(MLMC_EINVAL, "d_out is NULL");
-    const size_t need = level_workspace_bytes(n_chunks_of(args));
+    const size_t need = level_workspace_bytes(n_rows_of(args));
     if (d_workspace && workspace_bytes < need)
         return fail(MLMC_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
     DevState* st;
@@ -606,7 +608,7 @@ int mlmc_level_run(const mlmc_level_args_t* args, mlmc_result_t* out) {
     if (rc) return rc;
     DevState* st;
     if ((rc = device_state(&st))) return rc;
-    const size_t need = level_workspace_bytes(n_chunks_of(args));
+    const size_t need = level_workspace_bytes(n_rows_of(args));
     if ((rc = ensure_scratch(*st, need))) return rc;
     hipError_t e = hipEventRecord(st->ev0, st->stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -652,7 +654,7 @@ int mlmc_level_set_run(const mlmc_level_args_t* args, int n_calls, mlmc_result_t
     size_t total = up((size_t)n_calls * kPartial * sizeof(double));
     for (int i = 0; i < n_calls; ++i) {
         ws_off[i] = total;
-        total += up(level_workspace_bytes(n_chunks_of(&args[i])));
+        total += up(level_workspace_bytes(n_rows_of(&args[i])));
     }
     hipError_t e;
     for (hipStream_t& q : st->set_stream)
@@ -760,7 +762,7 @@ int mlmc_paths(const mlmc_level_args_t* args, double* d_pf_hat, double* d_pc_hat
     if (rc) return rc;
     DevState* st;
     if ((rc = device_state(&st))) return rc;
-    const size_t need = level_workspace_bytes(n_chunks_of(args));
+    const size_t need = level_workspace_bytes(n_rows_of(args));
     if ((rc = ensure_scratch(*st, need))) return rc;
     return enqueue_level(*st, args, v, nullptr, st->scratch, d_pf_hat, d_pc_hat, d_pf_bar, d_pc_bar, d_xf_tilde,
                          (hipStream_t)hip_stream);

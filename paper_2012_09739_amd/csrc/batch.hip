@@ -178,15 +178,8 @@ __device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const flo
             acc[kTerms + k] += t[k] * t[k];
         }
     }
-#pragma unroll
-    for (int k = 0; k < kPartial; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane < kPartial) {
-        double v = acc[0];
-#pragma unroll
-        for (int k = 1; k < kPartial; ++k)
-            if (lane == (uint32_t)k) v = acc[k];
-        prm.partials[chunk * kPartial + lane] = v;
-    }
+    // cooperative items are at least level 2, where a partial row is one chunk
+    store_row(acc, lane, prm.partials + chunk * kPartial);
 }
 
 template <int RV>
@@ -233,7 +226,7 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))
         if (lane == 0) t = atomicAdd(counter, 1u);
         t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, kWave));
         if (t >= n_tasks) break;
-        const uint4 task = tasks[t];  // (item, first chunk, chunk count, raised priority)
+        const uint4 task = tasks[t];  // (item, first row, row count, raised priority)
         const LevelParams& prm = params[task.x];
         const int var = variant[task.x];
         if (task.w) __builtin_amdgcn_s_setprio(3);
@@ -242,14 +235,14 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))
         const int v = var + (prm.n_steps < 4 ? 4 : 0);
         for (uint32_t c = task.y; c < task.y + task.z; ++c) {
             switch (v) {
-                case 0: run_chunk<MLMC_FP16, RV, true, false, false>(prm, c, lane, s_tab16, nullptr, s_ex); break;
-                case 1: run_chunk<MLMC_FP16, RV, true, true, false>(prm, c, lane, s_tab16, nullptr, s_ex); break;
-                case 2: run_chunk<MLMC_FP32, RV, true, false, false>(prm, c, lane, s_tab32, nullptr, s_ex); break;
-                case 3: run_chunk<MLMC_FP32, RV, true, true, false>(prm, c, lane, s_tab32, nullptr, s_ex); break;
-                case 4: run_chunk<MLMC_FP16, RV, true, false, false, true>(prm, c, lane, s_tab16, nullptr, s_ex); break;
-                case 5: run_chunk<MLMC_FP16, RV, true, true, false, true>(prm, c, lane, s_tab16, nullptr, s_ex); break;
-                case 6: run_chunk<MLMC_FP32, RV, true, false, false, true>(prm, c, lane, s_tab32, nullptr, s_ex); break;
-                default: run_chunk<MLMC_FP32, RV, true, true, false, true>(prm, c, lane, s_tab32, nullptr, s_ex); break;
+                case 0: run_row<MLMC_FP16, RV, true, false, false>(prm, c, lane, s_tab16, nullptr, s_ex); break;
+                case 1: run_row<MLMC_FP16, RV, true, true, false>(prm, c, lane, s_tab16, nullptr, s_ex); break;
+                case 2: run_row<MLMC_FP32, RV, true, false, false>(prm, c, lane, s_tab32, nullptr, s_ex); break;
+                case 3: run_row<MLMC_FP32, RV, true, true, false>(prm, c, lane, s_tab32, nullptr, s_ex); break;
+                case 4: run_row<MLMC_FP16, RV, true, false, false, true>(prm, c, lane, s_tab16, nullptr, s_ex); break;
+                case 5: run_row<MLMC_FP16, RV, true, true, false, true>(prm, c, lane, s_tab16, nullptr, s_ex); break;
+                case 6: run_row<MLMC_FP32, RV, true, false, false, true>(prm, c, lane, s_tab32, nullptr, s_ex); break;
+                default: run_row<MLMC_FP32, RV, true, true, false, true>(prm, c, lane, s_tab32, nullptr, s_ex); break;
             }
         }
         const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
@@ -303,7 +296,8 @@ mlmc_batch_cfg_t merged(const mlmc_batch_cfg_t* c) {
     return r;
 }
 
-// whether an item's chunks run cooperatively (binary32, at least coop_level; n_steps >= 4)
+// whether an item's chunks run cooperatively (binary32, at least coop_level; n_steps >= 4,
+// where a partial row is one chunk)
 bool is_coop(const mlmc_item_t& it, const mlmc_batch_cfg_t& c) {
     return it.precision == MLMC_FP32 && it.level >= c.coop_level && it.level >= 2;
 }
@@ -372,11 +366,13 @@ std::vector<uint4> build_tasks(const mlmc_batch& b, const std::vector<uint64_t>&
             for (uint64_t c = 0; c < rows[i]; ++c) cs.push_back({l, make_uint2((uint32_t)i, (uint32_t)c)});
             continue;
         }
-        const uint64_t per = std::max<uint64_t>(1, (uint64_t)b.cfg.task_steps >> l);
+        // rows of row_chunks(l) chunks: about task_steps steps per path and task
+        const uint64_t g = row_chunks(l);
+        const uint64_t per = std::max<uint64_t>(1, ((uint64_t)b.cfg.task_steps >> l) / g);
         const uint32_t prio = l >= b.cfg.priority_level ? 1u : 0u;
         for (uint64_t c = 0; c < rows[i]; c += per) {
             const uint64_t n = std::min<uint64_t>(per, rows[i] - c);
-            ts.push_back({n << l, make_uint4((uint32_t)i, (uint32_t)c, (uint32_t)n, prio)});
+            ts.push_back({(n * g) << l, make_uint4((uint32_t)i, (uint32_t)c, (uint32_t)n, prio)});
         }
     }
     std::stable_sort(ts.begin(), ts.end(), [](const T& a, const T& c) { return a.work > c.work; });
@@ -428,10 +424,17 @@ int prepare(mlmc_batch* b) {
     std::vector<uint64_t> rows(b->items.size());
     for (size_t i = 0; i < b->items.size(); ++i) {
         const uint64_t cp = chunk_paths(b->items[i].precision);
-        rows[i] = (b->items[i].n_paths + cp - 1) / cp;
+        rows[i] = rows_of((b->items[i].n_paths + cp - 1) / cp, b->items[i].level);
     }
     std::vector<uint2> coop;
     const std::vector<uint4> tasks = build_tasks(*b, rows, &coop);
+    // the 32-bit queue counters end at (tasks + waves) and (cooperative chunks + blocks): every
+    // wave (block) takes one index past the end before it leaves
+    const uint64_t waves = (uint64_t)b->n_cu * (uint64_t)b->cfg.waves_per_cu;
+    if ((uint64_t)tasks.size() + waves >= (1ull << 32) || (uint64_t)coop.size() + waves >= (1ull << 32))
+        return set_error(MLMC_EINVAL, "the plan needs %zu wave tasks and %zu cooperative chunks; at most 2^32 - %llu "
+                         "each fit the queue counters (fewer paths, or a larger task_steps)",
+                         tasks.size(), coop.size(), (unsigned long long)waves);
     int rc;
     if (tasks.size() > b->task_capacity || (b->d_tasks == nullptr && !tasks.empty())) {
         if (b->d_tasks) (void)hipFree(b->d_tasks);
@@ -509,7 +512,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
         if (it.stream > 0xFFFFu) return set_error(MLMC_EINVAL, "item %d: stream exceeds 65535", i);
         if (it.n_paths == 0 || it.n_paths > (1ull << 32))
             return set_error(MLMC_EINVAL, "item %d: n_paths must be 1..2^32", i);
-        total_rows += (it.n_paths + chunk_paths(it.precision) - 1) / chunk_paths(it.precision);
+        total_rows += rows_of((it.n_paths + chunk_paths(it.precision) - 1) / chunk_paths(it.precision), it.level);
     }
     const mlmc_batch_cfg_t c0 = merged(cfg);
     int rc = validate_cfg(c0);
@@ -539,7 +542,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
     uint64_t acc = 0;
     for (int i = 0; i < n_items; ++i) {
         const mlmc_item_t& it = items[i];
-        rows[i] = (it.n_paths + chunk_paths(it.precision) - 1) / chunk_paths(it.precision);
+        rows[i] = rows_of((it.n_paths + chunk_paths(it.precision) - 1) / chunk_paths(it.precision), it.level);
         off[i] = acc;
         acc += rows[i];
         var[i] = variant_of(it.precision, it.kahan);

@@ -40,7 +40,7 @@ struct LevelParams {
     const double* table64; // the same in binary64 (diagnostic)
     const void* mlp;       // MLP inference image (rv = MLP)
     const void* exact_tab; // ExactTable: rows of the exact inverse CDF, log cells
-    double* partials;      // [n_chunks][kPartial] chunk partial sums
+    double* partials;      // [n_rows][kPartial] partial sums of the rows (row_chunks chunks each)
     // optional per-path outputs (device, n_paths entries each, may be null)
     double* out_pf_hat;
     double* out_pc_hat;
@@ -61,13 +61,24 @@ struct Variant {
 
 // Launch helpers implemented in the .hip translation units.
 hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
-hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* stage, double* d_out, hipStream_t s);
+hipError_t launch_reduce(const double* partials, uint64_t n_rows, double* stage, double* d_out, hipStream_t s);
 
-// Workspace of one level call: the chunk partials and the stage rows of the two-stage
+// Chunks per partial row.  A row is the unit of the fixed-order reduction: a wave simulates
+// the row's chunks one after another, each lane adding its paths' terms in that order, then
+// reduces the row once.  At the coarse levels a chunk is only a few steps long, so the wave
+// reduction and the per-wave set-up would otherwise cost more than the paths; grouping depends
+// on the level alone, so every call and batch item of a level reduces its paths alike.
+__host__ __device__ inline uint32_t row_chunks(int level) { return level >= 2 ? 1u : (8u >> level); }
+__host__ __device__ inline uint64_t rows_of(uint64_t n_chunks, int level) {
+    const uint64_t g = row_chunks(level);
+    return (n_chunks + g - 1) / g;
+}
+
+// Workspace of one level call: the partial rows and the stage rows of the two-stage
 // reduction (at most 128 rows of kPartial doubles), plus 64 bytes of slack.
 constexpr uint64_t kStageRowsMax = 128;
-inline size_t level_workspace_bytes(uint64_t n_chunks) {
-    return (size_t)((n_chunks == 0 ? 1 : n_chunks) + kStageRowsMax) * kPartial * sizeof(double) + 64;
+inline size_t level_workspace_bytes(uint64_t n_rows) {
+    return (size_t)((n_rows == 0 ? 1 : n_rows) + kStageRowsMax) * kPartial * sizeof(double) + 64;
 }
 hipError_t launch_uniforms(uint64_t seed, uint32_t ctr2, uint32_t pset, uint64_t path0,
                            uint64_t n_paths, uint32_t n_steps, uint32_t* d_words, hipStream_t s);

@@ -11,20 +11,20 @@ namespace mlmc {
 
 namespace {
 
-// The two stages of the fixed-order reduction of n_chunks rows of 8 chunk partials (the
-// tree of reduce_stage1 / reduce_stage2).  The order depends only on n_chunks, so results do
+// The two stages of the fixed-order reduction of n_rows rows of 8 chunk partials (the
+// tree of reduce_stage1 / reduce_stage2).  The order depends only on n_rows, so results do
 // not depend on the level kernel's launch shape, and the batched sweep, which runs the same
 // stages per item, reproduces the single-level sums bit for bit.
 __global__ __launch_bounds__(kReduceBlock) void reduce_chunks_stage1(const double* __restrict__ partials,
-                                                                     uint64_t n_chunks, double* __restrict__ stage) {
+                                                                     uint64_t n_rows, double* __restrict__ stage) {
     __shared__ double s[kPartial][kReduceBlock];
-    reduce_stage1(partials, n_chunks, stage, blockIdx.x, s);
+    reduce_stage1(partials, n_rows, stage, blockIdx.x, s);
 }
 
 __global__ __launch_bounds__(kReduceBlock) void reduce_chunks_stage2(const double* __restrict__ stage,
-                                                                     uint64_t n_chunks, double* __restrict__ out) {
+                                                                     uint64_t n_rows, double* __restrict__ out) {
     __shared__ double s[kPartial][kReduceBlock];
-    reduce_stage2(stage, n_chunks, out, s);
+    reduce_stage2(stage, n_rows, out, s);
 }
 
 __global__ void uniforms_kernel(uint32_t k0, uint32_t k1, uint32_t ctr2, uint32_t pset, uint64_t path0,
@@ -86,12 +86,12 @@ int grid_for(uint64_t n, int block) {
 
 }  // namespace
 
-hipError_t launch_reduce(const double* partials, uint64_t n_chunks, double* stage, double* d_out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_chunks_stage1, dim3(stage_blocks(n_chunks)), dim3(kReduceBlock), 0, s, partials, n_chunks,
+hipError_t launch_reduce(const double* partials, uint64_t n_rows, double* stage, double* d_out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_chunks_stage1, dim3(stage_blocks(n_rows)), dim3(kReduceBlock), 0, s, partials, n_rows,
                        stage);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_chunks_stage2, dim3(1), dim3(kReduceBlock), 0, s, stage, n_chunks, d_out);
+    hipLaunchKernelGGL(reduce_chunks_stage2, dim3(1), dim3(kReduceBlock), 0, s, stage, n_rows, d_out);
     return hipGetLastError();
 }
 

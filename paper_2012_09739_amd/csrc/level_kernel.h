@@ -4,9 +4,9 @@
 // half2) and walks all 2^l fine steps of them: per group of four fine steps one Philox
 // call, then per step the exact and/or approximate variable, the fine update, and after
 // every second step the coarse update from the pairwise-summed variables (Section 3).
-// At the end each lane forms the payoffs and differences, and the wave reduces the
-// (sum, sum of squares) of every term into one chunk partial; a second kernel reduces
-// the chunk partials in a fixed order.
+// At the end each lane forms the payoffs and differences and adds them to its (sum, sum of
+// squares) of every term; after the chunks of one partial row (several at the coarse levels)
+// the wave reduces them into the row, and a second kernel reduces the rows in a fixed order.
 //
 // Arithmetic (Section 2.2): X <- X (+) (A (+) B), A = ca (x) X, B = (cb (x) X) (x) Z with
 // one rounding per operation (the build uses -ffp-contract=off), and the optional
@@ -124,10 +124,34 @@ __device__ __forceinline__ __half payoff_h(__half X, __half K, int kind) {
 }
 
 // ---- fixed-order wave reduction of the 8 partial values ------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
+// Lane i and lane i ^ 32 swap half of their eight values and each adds the half it keeps
+// (lanes with bit 5 clear keep values 0..3, the others 4..7); then i ^ 16 halves again and
+// i ^ 8 leaves one value per lane; a butterfly over the lowest three lane bits completes it.
+// Lane 8k ends with the total of value k.  The order of every addition depends on the lane
+// numbers only, so the result is reproducible; 10 exchanges of a double instead of the 48 of
+// eight separate butterflies.
+__device__ __forceinline__ void store_row(const double (&acc)[kPartial], uint32_t lane, double* out) {
+    static_assert(kPartial == 8, "three halving exchanges");
+    const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
+    double v4[4];
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-    return v;
+    for (int j = 0; j < 4; ++j) {
+        const double send = h5 ? acc[j] : acc[4 + j];
+        const double keep = h5 ? acc[4 + j] : acc[j];
+        v4[j] = keep + __shfl_xor(send, 32, kWave);
+    }
+    double v2[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double send = h4 ? v4[j] : v4[2 + j];
+        const double keep = h4 ? v4[2 + j] : v4[j];
+        v2[j] = keep + __shfl_xor(send, 16, kWave);
+    }
+    double v = (h3 ? v2[1] : v2[0]) + __shfl_xor(h3 ? v2[0] : v2[1], 8, kWave);
+    v += __shfl_xor(v, 4, kWave);
+    v += __shfl_xor(v, 2, kWave);
+    v += __shfl_xor(v, 1, kWave);
+    if ((lane & 7) == 0) out[lane >> 3] = v;
 }
 
 // Copies the first `bytes` of the exact-variable table (the top cells, then the log cells)
@@ -162,12 +186,12 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
 }
 
 // One wave simulates one chunk of 64 paths (128 for binary16: two paths per lane) of one
-// level and writes the chunk's 8 partial sums to prm.partials[chunk].  s_tab is the
+// level and adds each lane's (sum, sum of squares) of every term to acc.  s_tab is the
 // coefficient table in the working precision (binary32: prescaled, see prescaled_coeff) and
 // s_tab64 the binary64 one (diagnostic), both in LDS.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
-__device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
-                                          const double* s_tab64, const ExactLds* s_ex) {
+__device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
+                                            const double* s_tab64, const ExactLds* s_ex, double (&acc)[kPartial]) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kExactOnly = (RV == MLMC_RV_EXACT);
     constexpr bool kNeedExact = kExactOnly || NESTED;
@@ -302,9 +326,6 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
     }
 
     // payoffs and differences (binary64), then the lane's contribution to the sums
-    double acc[kPartial];
-#pragma unroll
-    for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
     const bool has_coarse = prm.level >= 1;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -358,15 +379,32 @@ __device__ __forceinline__ void run_chunk(const LevelParams& prm, uint64_t chunk
             }
         }
     }
+}
+
+// One wave runs partial row `row`: chunks row * g .. row * g + g - 1 (g = row_chunks(level),
+// those below the chunk count) one after another, each lane adding its terms in that order,
+// then one wave reduction into prm.partials[row].  The instances that serve only levels >= 2
+// (every one with the exact variable but the SHORT ones) have one-chunk rows, so their sums
+// need no registers during the steps.
+template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
+__device__ __forceinline__ void run_row(const LevelParams& prm, uint64_t row, uint32_t lane, const void* s_tab_v,
+                                        const double* s_tab64, const ExactLds* s_ex) {
+    constexpr bool kOneChunkRows = !SHORT && (NESTED || RV == MLMC_RV_EXACT);
+    double acc[kPartial];
 #pragma unroll
-    for (int k = 0; k < kPartial; ++k) acc[k] = wave_sum(acc[k]);
-    if (lane < kPartial) {
-        double v = acc[0];
-#pragma unroll
-        for (int k = 1; k < kPartial; ++k)
-            if (lane == (uint32_t)k) v = acc[k];
-        prm.partials[chunk * kPartial + lane] = v;
+    for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
+    if constexpr (kOneChunkRows) {
+        chunk_terms<PREC, RV, NESTED, KAHAN, DIAG, SHORT, SCHEME>(prm, row, lane, s_tab_v, s_tab64, s_ex, acc);
+    } else {
+        constexpr uint32_t kChunk = kWave * ((PREC == MLMC_FP16) ? 2 : 1);
+        const uint64_t n_chunks = (prm.n_paths + kChunk - 1) / kChunk;
+        const uint64_t g = row_chunks(prm.level);
+        const uint64_t c0 = row * g;
+        const uint64_t c1 = c0 + g < n_chunks ? c0 + g : n_chunks;
+        for (uint64_t c = c0; c < c1; ++c)
+            chunk_terms<PREC, RV, NESTED, KAHAN, DIAG, SHORT, SCHEME>(prm, c, lane, s_tab_v, s_tab64, s_ex, acc);
     }
+    store_row(acc, lane, prm.partials + row * kPartial);
 }
 
 // SHORT: the instance for levels with fewer than 4 fine steps (exact variables one word at a time).
@@ -424,9 +462,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == ML
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     constexpr uint32_t kChunk = kWave * L;
-    const uint64_t n_chunks = (prm.n_paths + kChunk - 1) / kChunk;
-    for (uint64_t chunk = wave; chunk < n_chunks; chunk += n_waves)
-        run_chunk<PREC, RV, NESTED, KAHAN, DIAG, SHORT, SCHEME>(prm, chunk, lane, tab, s_tab64, s_ex);
+    const uint64_t n_rows = rows_of((prm.n_paths + kChunk - 1) / kChunk, prm.level);
+    for (uint64_t row = wave; row < n_rows; row += n_waves)
+        run_row<PREC, RV, NESTED, KAHAN, DIAG, SHORT, SCHEME>(prm, row, lane, tab, s_tab64, s_ex);
 }
 
 }  // namespace mlmc

@@ -120,6 +120,53 @@ struct Chain<VALU_MED3_F32> {
     __device__ void step(float a, float b) { VR_32_3("v_med3_f32"); }
 };
 
+// further opcodes of the level kernels' loops (32-bit unless named otherwise)
+#define VR_CHAIN32(ID, T, BODY)                                  \
+    template <>                                                  \
+    struct Chain<ID> {                                           \
+        T r;                                                     \
+        __device__ void step(uint32_t a, uint32_t b) { BODY; }   \
+    };
+VR_CHAIN32(VALU_MIN_U32, uint32_t, VR_32_2("v_min_u32"))
+VR_CHAIN32(VALU_LSHL_OR_B32, uint32_t, VR_32_3("v_lshl_or_b32"))
+VR_CHAIN32(VALU_CNDMASK_B32, uint32_t,
+           asm volatile("v_cmp_gt_u32 vcc, %1, %2\n\tv_cndmask_b32 %0, %0, %1, vcc" : "+v"(r) : "v"(a), "v"(b) : "vcc"))
+VR_CHAIN32(VALU_PERM_B32, uint32_t, VR_32_3("v_perm_b32"))
+VR_CHAIN32(VALU_AND_B32, uint32_t, VR_32_2("v_and_b32"))
+VR_CHAIN32(VALU_ASHR_I32, uint32_t, VR_32_2("v_ashrrev_i32"))
+VR_CHAIN32(VALU_ADD_F16, uint32_t, VR_32_2("v_add_f16"))
+VR_CHAIN32(VALU_MUL_F16, uint32_t, VR_32_2("v_mul_f16"))
+VR_CHAIN32(VALU_PK_ADD_F16, uint32_t, VR_32_2("v_pk_add_f16"))
+VR_CHAIN32(VALU_CVT_PK_F16_F32, uint32_t, asm volatile("v_cvt_pk_f16_f32 %0, %1, %2" : "+v"(r) : "v"(a), "v"(b)))
+VR_CHAIN32(VALU_CVT_F32_U32, uint32_t, asm volatile("v_cvt_f32_u32 %0, %1" : "+v"(r) : "v"(a)))
+#undef VR_CHAIN32
+template <>
+struct Chain<VALU_CVT_F64_U32> {
+    double r;
+    __device__ void step(uint32_t a, uint32_t) { asm volatile("v_cvt_f64_u32 %0, %1" : "+v"(r) : "v"(a)); }
+};
+template <>
+struct Chain<VALU_LSHL_B64> {
+    uint64_t r;
+    __device__ void step(uint32_t a, uint32_t) { asm volatile("v_lshlrev_b64 %0, %1, %0" : "+v"(r) : "v"(a)); }
+};
+template <>
+struct Chain<VALU_LSHL_ADD_U64> {
+    uint64_t r;
+    __device__ void step(uint32_t a, uint32_t) {
+        const uint64_t c = 0x100000001ull;
+        asm volatile("v_lshl_add_u64 %0, %0, 1, %1" : "+v"(r) : "v"(c));
+    }
+};
+template <>
+struct Chain<VALU_MOV_B64> {
+    uint64_t r;
+    __device__ void step(uint32_t a, uint32_t) {
+        const uint64_t c = 0x100000001ull + a;
+        asm volatile("v_mov_b64 %0, %1" : "+v"(r) : "v"(c));
+    }
+};
+
 // the 32x32->64 integer product in the form Philox uses it: a lane value times a uniform
 // (SGPR) multiplier, zero addend
 template <>
@@ -169,7 +216,9 @@ __device__ void seed(Chain<OP>& c, uint32_t lane, int k) {
         c.r = 1.0f;
         c.h = (uint32_t)k;
     } else if constexpr (sizeof(T) == 8) c.r = 1.0 + 1e-3 * (double)(lane + k);
-    else if constexpr (OP == VALU_PK_FMA_F16 || OP == VALU_PK_MUL_F16 || OP == VALU_FMA_F16) c.r = 0x3C003C00u + k;
+    else if constexpr (OP == VALU_PK_FMA_F16 || OP == VALU_PK_MUL_F16 || OP == VALU_FMA_F16 || OP == VALU_ADD_F16 ||
+                       OP == VALU_MUL_F16 || OP == VALU_PK_ADD_F16)
+        c.r = 0x3C003C00u + k;
     else if constexpr (std::is_same<T, float>::value) c.r = 1.0f + 1e-3f * (float)(lane + k);
     else c.r = lane * 747796405u + (uint32_t)k;
 }
@@ -182,10 +231,7 @@ __global__ __launch_bounds__(256) void probe_kernel(uint32_t iters, uint64_t* si
     for (int k = 0; k < kChains; ++k) seed<OP>(c[k], lane, k);
     // operands near one keep the floating-point chains finite and normal
     using T = decltype(c[0].r);
-    auto a = (OP == VALU_MAD_U64_U32 || OP == VALU_XOR3_B32 || OP == VALU_ADD_U32 || OP == VALU_MUL_LO_U32 ||
-              OP == VALU_MUL_HI_U32 || OP == VALU_FFBH_U32)
-                 ? (uint32_t)(lane | 1u)
-                 : 0u;
+    const uint32_t a = lane | 1u;
     const double af64 = 0.999999, bf64 = 1e-7;
     const float af32 = 0.999999f, bf32 = 1e-7f;
     const uint32_t ah = 0x3BFF3BFFu, bh = 0x00010001u;  // half2 (0.9995, 0.9995), (tiny, tiny)
@@ -196,8 +242,11 @@ __global__ __launch_bounds__(256) void probe_kernel(uint32_t iters, uint64_t* si
             for (int k = 0; k < kChains; ++k) {
                 if constexpr (sizeof(T) == 8 && OP != VALU_MAD_U64_U32) c[k].step(af64, bf64);
                 else if constexpr (OP == VALU_MAD_U64_U32) c[k].step(a, 0xD2511F53u);
-                else if constexpr (OP == VALU_PK_FMA_F16 || OP == VALU_PK_MUL_F16 || OP == VALU_FMA_F16)
+                else if constexpr (OP == VALU_PK_FMA_F16 || OP == VALU_PK_MUL_F16 || OP == VALU_FMA_F16 ||
+                                   OP == VALU_ADD_F16 || OP == VALU_MUL_F16 || OP == VALU_PK_ADD_F16)
                     c[k].step(ah, bh);
+                else if constexpr (OP == VALU_CVT_PK_F16_F32)
+                    c[k].step(__float_as_uint(af32), __float_as_uint(bf32));
                 else if constexpr (std::is_same<T, float>::value) c[k].step(af32, bf32);
                 else c[k].step(a, a ^ 0x9E3779B9u);
             }
@@ -219,7 +268,9 @@ hipError_t launch(uint32_t grid, uint32_t iters, uint64_t* sink, hipStream_t s) 
 }
 
 // instructions of the opcode per loop trip and chain (the conversion probes run two)
-int instrs_per_step(int op) { return (op == VALU_CVT_F64_F32 || op == VALU_CVT_F16_F32) ? 2 : 1; }
+int instrs_per_step(int op) {
+    return (op == VALU_CVT_F64_F32 || op == VALU_CVT_F16_F32 || op == VALU_CNDMASK_B32) ? 2 : 1;
+}
 
 }  // namespace
 
@@ -255,7 +306,11 @@ extern "C" int valu_rate(int op, int waves_per_simd, uint32_t iters, double* lan
             VR_CASE(VALU_MUL_F32) VR_CASE(VALU_PK_FMA_F16) VR_CASE(VALU_PK_MUL_F16) VR_CASE(VALU_FMA_F16)
             VR_CASE(VALU_XOR3_B32) VR_CASE(VALU_ADD_U32) VR_CASE(VALU_MUL_LO_U32) VR_CASE(VALU_MUL_HI_U32)
             VR_CASE(VALU_FFBH_U32) VR_CASE(VALU_EXP_F32) VR_CASE(VALU_RCP_F32) VR_CASE(VALU_MED3_F32)
-            VR_CASE(VALU_MAD_U64_U32) VR_CASE(VALU_CVT_F64_F32) VR_CASE(VALU_CVT_F16_F32)
+            VR_CASE(VALU_MAD_U64_U32) VR_CASE(VALU_CVT_F64_F32) VR_CASE(VALU_CVT_F16_F32) VR_CASE(VALU_MIN_U32)
+            VR_CASE(VALU_LSHL_OR_B32) VR_CASE(VALU_CNDMASK_B32) VR_CASE(VALU_PERM_B32) VR_CASE(VALU_AND_B32)
+            VR_CASE(VALU_ASHR_I32) VR_CASE(VALU_ADD_F16) VR_CASE(VALU_MUL_F16) VR_CASE(VALU_PK_ADD_F16)
+            VR_CASE(VALU_CVT_PK_F16_F32) VR_CASE(VALU_CVT_F32_U32) VR_CASE(VALU_CVT_F64_U32) VR_CASE(VALU_LSHL_B64)
+            VR_CASE(VALU_LSHL_ADD_U64) VR_CASE(VALU_MOV_B64)
 #undef VR_CASE
             default: e = hipErrorInvalidValue;
         }
