@@ -169,14 +169,14 @@ int upload_tables(DevState& st) {
     for (int r = 0; r < 2; ++r) {
         const double(*src)[4] = r == 0 ? ht.pwl : ht.cubic;
         const int d = r == 0 ? 1 : 3;
-        const int n = 16 * (d + 1);
-        double h64[64];
-        float h32[64];
-        __half h16[64];
-        float hbf[64];
-        for (int j = 0; j < 16; ++j)
+        const int n = kTableRowsDev * (d + 1);  // device layout: rows 15..31 repeat interval 16
+        double h64[kTableRowsDev * 4];
+        float h32[kTableRowsDev * 4];
+        __half h16[kTableRowsDev * 4];
+        float hbf[kTableRowsDev * 4];
+        for (int j = 0; j < kTableRowsDev; ++j)
             for (int i = 0; i <= d; ++i) {
-                const double c = src[j][i];
+                const double c = src[j < kTableRows ? j : kTableRows - 1][i];
                 h64[j * (d + 1) + i] = c;
                 h32[j * (d + 1) + i] = (float)c;
                 h16[j * (d + 1) + i] = half_of(c);  // one rounding from binary64

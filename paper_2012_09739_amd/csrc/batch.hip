@@ -190,14 +190,14 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))
                                                     const __half* __restrict__ tab16, const void* __restrict__ exact_tab,
                                                     unsigned long long* __restrict__ ticks) {
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
-    __shared__ float s_tab32[kTableRows * 4];
-    __shared__ __half s_tab16[kTableRows * 4];
+    __shared__ float s_tab32[kTableRowsDev * 4];
+    __shared__ __half s_tab16[kTableRowsDev * 4];
     __shared__ __align__(16) unsigned char s_ex_raw[sizeof(ExactCols)];
     __shared__ double ring_x[2][kCoopSteps][kWave];
     __shared__ float ring_b[2][kCoopSteps][kWave];
     __shared__ uint32_t s_pop;
     const ExactLds* s_ex = (const ExactLds*)s_ex_raw;  // the top rows only (no learned variable here)
-    for (int i = threadIdx.x; i < kTableRows * (DEG + 1); i += blockDim.x) {
+    for (int i = threadIdx.x; i < kTableRowsDev * (DEG + 1); i += blockDim.x) {
         s_tab32[i] = prescaled_coeff(tab32[i], i % (DEG + 1));
         s_tab16[i] = tab16[i];
     }

@@ -195,6 +195,7 @@ struct DyadicPos {
 // a = 2 xm + 1, clz(a) = k - 1 and, for s = min(k - 1, 14),
 //   k <= 15:  (a << s) mod 2^31 = (xm << k) - 2^31 + 2^(k-1)    (u' = 2^-(k+1) (1 + t))
 //   k >= 16:  (a << s)          = (xm << 15) + 2^14             (u' = 2^-16 t)
+// The row is k - 1 itself: the device tables repeat the last interval's row in rows 15..31.
 __device__ __forceinline__ DyadicPos dyadic_locate(uint32_t word) {
     DyadicPos p;
     p.sign = word & 0x80000000u;
@@ -202,7 +203,7 @@ __device__ __forceinline__ DyadicPos dyadic_locate(uint32_t word) {
     const uint32_t a = (xm << 1) | 1u;
     const uint32_t km1 = (uint32_t)__builtin_clz(a);  // a != 0
     p.T = (a << (km1 < 14u ? km1 : 14u)) & 0x7FFFFFFFu;
-    p.row = km1 < 15u ? km1 : 15u;
+    p.row = km1;
     return p;
 }
 
@@ -288,7 +289,7 @@ __device__ __forceinline__ __half icdf_dyadic_f16(uint32_t word, const __half* _
         q = __hmul(q, t);
         q = __hadd(q, c[i]);
     }
-    return p.sign ? __hneg(q) : q;
+    return __ushort_as_half((unsigned short)(__half_as_ushort(q) ^ (p.sign >> 16)));
 }
 
 // ---- piecewise-constant variable (table lookup) ------------------------------------------

@@ -15,6 +15,9 @@ constexpr int kPartial = 2 * kTerms;  // (sum, sum of squares) per term
 constexpr int kWave = 64;
 constexpr int kMaxLevel = 24;
 constexpr int kTableRows = 16;
+// Device layout of a dyadic table: row r serves clz(2 xm + 1) = r, so rows 15..31 all hold
+// the coefficients of the last interval (0, 2^-16) and the row needs no clamp.
+constexpr int kTableRowsDev = 32;
 // piecewise-constant variable: 2^kPcBits equal cells of (0, 1), the lower half stored
 constexpr int kPcBits = 12;
 constexpr int kPcEntries = 1 << (kPcBits - 1);

@@ -251,8 +251,20 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
         double zx[L][4];
         if constexpr (kNeedExact) {
             if constexpr (!SHORT) {
+                // the exact pair of one path at a time: its four variables, then its four fine
+                // and two coarse steps in step order (the binary16 lanes' second path reuses
+                // the registers of the first)
 #pragma unroll
-                for (int l = 0; l < L; ++l) icdf_exact_f64x4(r[l].w, zx[l], &s_ex->top, deep_rows(prm), kc);
+                for (int l = 0; l < L; ++l) {
+                    double z4[4];
+                    icdf_exact_f64x4(r[l].w, z4, &s_ex->top, deep_rows(prm), kc);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        em_step<SCHEME, double>(Xfh[l], z4[i], ca64, prm.cb_f64, prm.cm_f64, 1.0);
+                        if (i & 1) em_step<SCHEME, double>(Xch[l], zh_prev[l] + z4[i], cac64, prm.cb_f64, prm.cm_f64, 2.0);
+                        else zh_prev[l] = z4[i];
+                    }
+                }
             } else {
                 // levels 0 and 1 use only the first one or two words of the call
 #pragma unroll
@@ -269,7 +281,7 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
             if constexpr (SHORT || !kNeedExact)
                 if (4 * q + i >= prm.n_steps) break;
             const bool coarse = (i & 1) != 0;
-            if constexpr (kNeedExact) {
+            if constexpr (kNeedExact && SHORT) {
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     const double z = zx[l][i];
@@ -410,7 +422,7 @@ __device__ __forceinline__ void run_row(const LevelParams& prm, uint64_t row, ui
 // SHORT: the instance for levels with fewer than 4 fine steps (exact variables one word at a time).
 // SCHEME: MLMC_SCHEME_EM or MLMC_SCHEME_MILSTEIN.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == MLMC_FP32 || PREC == MLMC_FP64) && RV != MLMC_RV_MLP && !SHORT ? 7 : 1))) void level_kernel(const LevelParams prm) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RV == MLMC_RV_MLP || SHORT ? 1 : (PREC == MLMC_FP32 || PREC == MLMC_FP64) ? 7 : PREC == MLMC_FP16 ? 6 : 1))) void level_kernel(const LevelParams prm) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
     constexpr bool kPconst = (RV == MLMC_RV_PCONST4096);
@@ -419,7 +431,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((PREC == ML
 
     // coefficient tables or cell means in LDS (working precision, and binary64 for the
     // diagnostic), each sized for the variant that reads it
-    constexpr int kTabN = kPconst ? kPcEntries : kTableRows * (DEG + 1);
+    constexpr int kTabN = kPconst ? kPcEntries : kTableRowsDev * (DEG + 1);
     constexpr bool kTab16 = PREC == MLMC_FP16 && (kDyadic || kPconst);
     __shared__ AT s_tab[(kDyadic || kPconst) && !kTab16 ? kTabN : 1];
     __shared__ __half s_tab16[kTab16 ? kTabN : 1];
