@@ -99,7 +99,9 @@ REPORT_LEGS = ("plain", "fp16", "batch", "mlp", "sweep", "adaptive", "milstein",
 VALU_OPS = ("v_fma_f64", "v_mul_f64", "v_add_f64", "v_fma_f32", "v_mul_f32", "v_pk_fma_f16", "v_pk_mul_f16",
             "v_fma_f16", "v_bitop3_b32 (xor3)", "v_add_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_ffbh_u32",
             "v_exp_f32", "v_rcp_f32", "v_med3_f32", "v_mad_u64_u32", "v_cvt_f32_f64 + v_cvt_f64_f32",
-            "v_cvt_f16_f32 + v_cvt_f32_f16")
+            "v_cvt_f16_f32 + v_cvt_f32_f16", "v_min_u32", "v_lshl_or_b32", "v_cmp_gt_u32 + v_cndmask_b32",
+            "v_perm_b32", "v_and_b32", "v_ashrrev_i32", "v_add_f16", "v_mul_f16", "v_pk_add_f16", "v_cvt_pk_f16_f32",
+            "v_cvt_f32_u32", "v_cvt_f64_u32", "v_lshlrev_b64", "v_lshl_add_u64", "v_mov_b64")
 
 
 def parse():
@@ -427,12 +429,23 @@ def reports(M, E, torch, legs=REPORT_LEGS):
         torch.cuda.synchronize()
         mlp_rows = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_NESTED_MLP, 0)
         pwl_rows = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0)
+        mlp_two = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_APPROX_MLP, 0)
+        pwl_two = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP32, M.MLMC_APPROX_PWL16, 0)
+        plain = _level_costs(M, call, W.MLP_LEVELS, W.MLP_PATHS, M.MLMC_FP64, M.MLMC_EXACT, 0)
+        # equal-variance time of the nested estimator (Section 3) with each approximate variable
+        speed = {tag: E.speedup_equal_variance(var(plain, 0), cost(plain), var(two, 0), cost(two), var(nest, 1),
+                                               cost(nest))
+                 for tag, two, nest in (("mlp", mlp_two, mlp_rows), ("pwl16", pwl_two, pwl_rows))}
         rep["mlp_nested_fp32_levels0to10_2p22"] = {
             "train_seconds": train_s, "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
             "mse_Z_minus_Ztilde": {"mlp": float(((zs[M.MLMC_RV_MLP] - zs[M.MLMC_RV_EXACT]) ** 2).mean()),
                                    "pwl16": float(((zs[M.MLMC_RV_PWL16] - zs[M.MLMC_RV_EXACT]) ** 2).mean())},
             "four_way_var": {"mlp": var(mlp_rows, 1), "pwl16": var(pwl_rows, 1)},
-            "nested_path_steps_per_s": {"mlp": rate(mlp_rows), "pwl16": rate(pwl_rows)}}
+            "nested_path_steps_per_s": {"mlp": rate(mlp_rows), "pwl16": rate(pwl_rows)},
+            "nested_rate_mlp_over_pwl16": rate(mlp_rows) / rate(pwl_rows),
+            "approx_two_way_path_steps_per_s": {"mlp": rate(mlp_two), "pwl16": rate(pwl_two)},
+            "speedup_T_hat_over_T_bar": speed,
+            "time_gain_mlp_over_pwl16": speed["mlp"] / speed["pwl16"]}
     if "sweep" in legs:
         # precision-width sweep (Figure 3's question): variance of the rounding difference
         # X-_N - X~_N against the level for bfloat16 (8 bits), binary16 (11) and binary32 (24),

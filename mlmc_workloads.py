@@ -45,12 +45,16 @@ def batch_parameter_sets(n=BATCH_PSETS, seed=0):
 
 
 def mlp_initial_params(seed=0):
-    """Initial weights of the 1-16-16-1 network (Glorot-uniform scale, zero biases)."""
+    """Initial weights of the 1-16-16-1 hard-tanh network: first-layer slopes |W1| ~ U[2, 6]
+    with random signs and biases b1 ~ U(-1, 1) |W1|, so that every unit's two kinks
+    (W1 x + b1 = +-1) fall near the input range [-1, 1]; W2 ~ U(-1, 1); output weights at
+    the Glorot-uniform scale; zero b2, b3."""
     rng = np.random.default_rng(seed)
-    w1 = rng.uniform(-1, 1, 16) * np.sqrt(6 / 17)
-    w2 = rng.uniform(-1, 1, 256) * np.sqrt(6 / 32)
+    w1 = rng.uniform(2.0, 6.0, 16) * rng.choice([-1.0, 1.0], 16)
+    b1 = rng.uniform(-1.0, 1.0, 16) * np.abs(w1)
+    w2 = rng.uniform(-1.0, 1.0, 256)
     w3 = rng.uniform(-1, 1, 16) * np.sqrt(6 / 17)
-    return np.concatenate([w1, np.zeros(16), w2, np.zeros(16), w3, [0.0]]).astype(np.float64)
+    return np.concatenate([w1, b1, w2, np.zeros(16), w3, [0.0]]).astype(np.float64)
 
 
 def sampled_paths(n_paths, k=64, seed=1):

@@ -1,26 +1,44 @@
-"""The learned approximate inverse CDF: a 1-16-16-1 tanh network (test infrastructure only).
+"""The learned approximate inverse CDF: a 1-16-16-1 piecewise-linear network (test
+infrastructure only).
 
 Section 2.1 admits any approximate Gaussian variable that satisfies Assumption 2.1 (zero
 mean, bounded, finite moments, bounded density with finitely many discontinuities).  This
-module restates, in float64, the small network used as such an approximation:
+module restates, in float64, the small network used as such an approximation.
+
+Training form (the binary32 master parameters), with the hard tanh ht(z) = min(max(z, -1), 1):
 
     u' = min(u, 1 - u)                        (mirror: exact zero mean, like Figure 1)
     r  = sqrt(-2 ln(2 u'))                    (r in [0, 6.7] for 32-bit words)
     x  = r / R_SCALE - 1                      (network input)
-    h1 = tanh(W1 x + b1)                      (16)
-    h2 = tanh(W2 h1 + b2)                     (16 x 16)
+    h1 = ht(W1 x + b1)                        (16)
+    h2 = ht(W2 h1 + b2)                       (16 x 16)
     y  = W3 . h2 + b3                         (learns Phi^{-1}(u') + r, a smooth function
                                                of r with values in [0, 0.52])
     Z~ = y - r for u < 1/2, r - y for u >= 1/2
 
-Z~ is bounded for the law of 32-bit words (r <= 6.7, |y| <= |b3| + sum |W3|), so
-Assumption 2.1's boundedness holds.  Parameters are one flat vector of 321 values in the
-order W1(16), b1(16), W2(16x16, row-major [out][in]), b2(16), W3(16), b3(1).  Training
-minimises the mean squared error of y against Phi^{-1}(u') + r with Adam (Kingma and
-Ba, 2015) on pairs drawn by ``training_words``.
+Deployed form (what the level kernels evaluate): the same function with the clamp to [0, 1]
+as activation, c = (h + 1) / 2, so that each activation is the clamp output modifier of the
+instruction that forms its argument:
+
+    c1 = clamp01(A1 x + a1),  c2 = clamp01(A2 c1 + a2),  y = A3 . c2 + a3,
+    A1 = W1 / 2, a1 = (b1 + 1) / 2, A2 = W2, a2 = (b2 - W2 1 + 1) / 2, A3 = 2 W3, a3 = b3 - W3 . 1
+
+formed in binary32 (sums in index order) and rounded once to binary16.  Inference: the input
+2u' is the word's 2 xm + 1 rounded to binary32 times 2^-32, r = sqrt(-2 ln 2u'), x = r C - 1
+with C = R_32(1 / R_SCALE), rounded to binary16; the first layer is one binary16 fused
+multiply-add per unit (a single rounding); the 16 x 16 layer takes binary16 activations and
+accumulates in binary32 (here: exactly); the output layer is binary32 (here: exact).
+
+Z~ is bounded for the law of 32-bit words (r <= 6.7, |y| <= |a3| + sum |A3|), so Assumption
+2.1's boundedness holds.  Parameters are one flat vector of 321 values in the order W1(16),
+b1(16), W2(16x16, row-major [out][in]), b2(16), W3(16), b3(1) (the deployed form uses the
+same layout for A1, a1, A2, a2, A3, a3).  Training minimises the mean squared error of y
+against Phi^{-1}(u') + r with Adam (Kingma and Ba, 2015) on pairs drawn by
+``training_words``.
 
 Pinned by ``tests/test_oracle_mlp.py``: back-propagated gradients against central finite
-differences, and the Adam update against its published closed form on a scalar problem.
+differences, the Adam update against its closed form on a scalar problem, and the deployed
+form equal to the training form without rounding.
 """
 
 import numpy as np
@@ -31,6 +49,8 @@ N_HIDDEN = 16
 N_PARAMS = 16 + 16 + 256 + 16 + 16 + 1
 R_SCALE = 3.4
 ADAM_BETA1, ADAM_BETA2, ADAM_EPS = 0.9, 0.999, 1e-8
+# the input scale of inference, 1 / R_SCALE rounded to binary32
+C_INPUT = float(np.float32(1.0 / R_SCALE))
 
 
 def unpack(p):
@@ -51,20 +71,31 @@ def pack(W1, b1, W2, b2, W3, b3):
     return np.concatenate([W1, b1, np.asarray(W2).reshape(-1), b2, W3, [b3]]).astype(np.float64)
 
 
+def hard_tanh(z):
+    return np.clip(z, -1.0, 1.0)
+
+
+def hard_tanh_slope(z):
+    """Derivative of the hard tanh: 1 inside (-1, 1), 0 outside (and at the kinks)."""
+    return ((z > -1.0) & (z < 1.0)).astype(np.float64)
+
+
 def feature(u_half):
-    """x = sqrt(-2 ln(2 u')) / R_SCALE - 1 for u' in (0, 1/2]."""
+    """x = sqrt(-2 ln(2 u')) / R_SCALE - 1 for u' in (0, 1/2] (the training input)."""
     u_half = np.asarray(u_half, dtype=np.float64)
     return np.sqrt(-2.0 * np.log(2.0 * u_half)) / R_SCALE - 1.0
 
 
 def forward(p, x):
-    """Network output y and the activations needed by ``backward``."""
+    """Network output y of the training form and the values needed by ``backward``."""
     W1, b1, W2, b2, W3, b3 = unpack(p)
     x = np.asarray(x, dtype=np.float64)
-    h1 = np.tanh(np.outer(x, W1) + b1)          # (B, 16)
-    h2 = np.tanh(h1 @ W2.T + b2)                # (B, 16)
+    z1 = np.outer(x, W1) + b1                   # (B, 16)
+    h1 = hard_tanh(z1)
+    z2 = h1 @ W2.T + b2                         # (B, 16)
+    h2 = hard_tanh(z2)
     y = h2 @ W3 + b3
-    return y, (x, h1, h2)
+    return y, (x, z1, h1, z2, h2)
 
 
 def loss(p, x, target):
@@ -76,15 +107,13 @@ def loss(p, x, target):
 def backward(p, cache, dy):
     """Gradient of sum_b dy_b * y_b with respect to the parameters (chain rule)."""
     W1, b1, W2, b2, W3, b3 = unpack(p)
-    x, h1, h2 = cache
+    x, z1, h1, z2, h2 = cache
     dW3 = h2.T @ dy
     db3 = np.sum(dy)
-    dh2 = np.outer(dy, W3)
-    da2 = dh2 * (1.0 - h2 * h2)
+    da2 = np.outer(dy, W3) * hard_tanh_slope(z2)
     dW2 = da2.T @ h1
     db2 = da2.sum(axis=0)
-    dh1 = da2 @ W2
-    da1 = dh1 * (1.0 - h1 * h1)
+    da1 = (da2 @ W2) * hard_tanh_slope(z1)
     dW1 = da1.T @ x
     db1 = da1.sum(axis=0)
     return pack(dW1, db1, dW2, db2, dW3, db3)
@@ -132,25 +161,79 @@ def training_pairs(seed, first, n):
 
 
 def mirror(x_words):
-    """(upper-half flag, u' = min(u, 1-u)) for uint32 words, u = (x + 1/2) 2^-32."""
+    """(upper-half flag, mirrored word xm) for uint32 words: xm = 2^32 - 1 - x on the upper half."""
     x = np.asarray(x_words, dtype=np.uint64)
     s = x >= np.uint64(2 ** 31)
-    xm = np.where(s, np.uint64(2 ** 32 - 1) - x, x)
-    return s, (xm.astype(np.float64) + 0.5) * 2.0 ** -32
+    return s, np.where(s, np.uint64(2 ** 32 - 1) - x, x)
+
+
+def fold(p, rounding=np.float32):
+    """The deployed (clamp to [0, 1]) form of training parameters p, formed in the given
+    arithmetic (binary32: one rounding per operation, sums in index order; float64 for the
+    unrounded algebra)."""
+    f = rounding
+    W1, b1, W2, b2, W3, b3 = (np.asarray(a, dtype=np.float64).astype(f) for a in unpack(p))
+    b3 = f(b3)
+    half, one, two = f(0.5), f(1.0), f(2.0)
+    A1 = W1 * half
+    a1 = (b1 + one) * half
+    a2 = np.empty(16, dtype=f)
+    for n in range(16):
+        s = f(0.0)
+        for k in range(16):
+            s = f(s + W2[n, k])
+        a2[n] = f(f(f(b2[n] - s) + one) * half)
+    t = f(0.0)
+    for k in range(16):
+        t = f(t + W3[k])
+    return pack(A1, a1, W2, a2, W3 * two, f(b3 - t))
 
 
 def deployed(p):
-    """The inference model: parameters rounded once to binary16."""
-    return np.asarray(p, dtype=np.float64).astype(np.float16).astype(np.float64)
+    """The inference model: the deployed form of p (binary32) rounded once to binary16."""
+    return fold(p).astype(np.float16).astype(np.float64)
 
 
-def approx_icdf(x_words, p16, precision):
-    """Z~ for uint32 words from the binary16-rounded parameters, evaluated in float64 and
-    rounded once to precision p."""
+def radius(xm):
+    """(r, 2u'') with 2u'' = R_32(2 xm + 1) 2^-32 and r = sqrt(-2 ln 2u'')."""
+    a = (2 * np.asarray(xm, dtype=np.uint64) + np.uint64(1)).astype(np.float32).astype(np.float64)
+    two_u = a * 2.0 ** -32
+    return np.sqrt(-2.0 * np.log(two_u)), two_u
+
+
+def input16(r):
+    """The binary16 network input R_16(r C - 1) of inference (from the unrounded r C - 1)."""
+    return (r * C_INPUT - 1.0).astype(np.float16).astype(np.float64)
+
+
+def eval_deployed(q, x16):
+    """y of the deployed model q at binary16 inputs x16: the first layer's fused binary16
+    multiply-add (exact in float64, rounded once), the other layers exact."""
+    A1, a1, A2, a2, A3, a3 = unpack(q)
+    z1 = (np.outer(x16, A1) + a1).astype(np.float16).astype(np.float64)
+    c1 = np.clip(z1, 0.0, 1.0)
+    c2 = np.clip(c1 @ A2.T + a2, 0.0, 1.0)
+    return c2 @ A3 + a3
+
+
+def approx_icdf(x_words, q, precision, x16=None):
+    """Z~ for uint32 words from the deployed model q (binary16 values), rounded once to
+    precision p.  x16 (optional) replaces the binary16 inputs of the words."""
     shape = np.shape(x_words)
-    s, uh = mirror(np.ravel(x_words))
-    r = np.sqrt(-2.0 * np.log(2.0 * uh))
-    y, _ = forward(p16, r / R_SCALE - 1.0)
-    q = y - r
-    z = np.where(s, -q, q).reshape(shape)
+    s, xm = mirror(np.ravel(x_words))
+    r, _ = radius(xm)
+    xi = input16(r) if x16 is None else np.ravel(x16)
+    z = eval_deployed(q, xi) - r
+    z = np.where(s, -z, z).reshape(shape)
     return fp.rn(precision, z)
+
+
+def input16_neighbours(x_words, delta):
+    """For each word, the binary16 roundings of every value within delta of r C - 1: (lo, hi),
+    equal unless r C - 1 lies within delta of a rounding boundary of binary16."""
+    _, xm = mirror(np.ravel(x_words))
+    r, _ = radius(xm)
+    x = r * C_INPUT - 1.0
+    lo = (x - delta).astype(np.float16).astype(np.float64)
+    hi = (x + delta).astype(np.float16).astype(np.float64)
+    return lo, hi

@@ -35,8 +35,10 @@ EXTRA_FLAGS = {"level_f16.hip": ["-fno-slp-vectorize"], "level_milstein_f16.hip"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I" + os.path.join(ROOT, "include"),
           "-I" + CSRC, "-Wall", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
+# matrix instructions (the learned variable's 16 x 16 layer) read and write VGPRs directly,
+# with no copies out of accumulation registers
 HIP_FLAGS = ["--offload-arch=gfx950", "-x", "hip", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-fno-gpu-rdc"]
+             "-fno-gpu-rdc", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _hipcc():

@@ -119,7 +119,7 @@ __device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const flo
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     ring_x[f & 1][base + i][lane] = zx[i];
-                    ring_b[f & 1][base + i][lane] = approx_rv<RV, DEG, float, MLMC_FP32>(r.w[i], s_tab, nullptr, nullptr);
+                    ring_b[f & 1][base + i][lane] = approx_rv<RV, DEG, float, MLMC_FP32>(r.w[i], s_tab, nullptr);
                 }
             }
             __syncthreads();  // phase f written; the consumer is done with slot (f + 1) & 1

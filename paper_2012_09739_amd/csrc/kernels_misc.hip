@@ -63,7 +63,7 @@ __global__ void icdf_kernel(const uint32_t* __restrict__ words, uint64_t n, cons
             else if constexpr (PREC == MLMC_FP16) z = (double)__half2float(icdf_pconst_f16(w, (const __half*)table));
             else z = (double)icdf_pconst_f32(w, (const float*)table);
         } else if constexpr (RV == MLMC_RV_MLP) {
-            const float y = icdf_mlp_f32(w, (const float*)mlp, ex->lds.log);
+            const float y = icdf_mlp_f32(w, (const float*)mlp);
             if constexpr (PREC == MLMC_FP16) z = (double)__half2float(__float2half_rn(y));
             else z = (double)y;
         } else if constexpr (PREC == MLMC_FP64) {

@@ -170,9 +170,9 @@ __device__ __forceinline__ const double (*deep_rows(const LevelParams& prm))[kRo
 // ---- the kernel ------------------------------------------------------------------------
 // Approximate variable of one word in the working precision (binary64 or binary32).
 template <int RV, int DEG, typename T, int PREC = MLMC_FP32>
-__device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* mlpw, const LogCell* logtab) {
+__device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* mlpw) {
     if constexpr (RV == MLMC_RV_MLP) {
-        return (T)icdf_mlp_f32(w, mlpw, logtab);
+        return (T)icdf_mlp_f32(w, mlpw);
     } else if constexpr (RV == MLMC_RV_PCONST4096) {
         if constexpr (sizeof(T) == 8) return icdf_pconst_f64(w, (const double*)tab);
         else return icdf_pconst_f32(w, (const float*)tab);  // binary32, or bfloat16 values held in binary32
@@ -292,7 +292,7 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
                 }
             }
             if constexpr (kNeedApprox && PREC != MLMC_FP16) {
-                const AT z = approx_rv<RV, DEG, AT, PREC>(r[0].w[i], s_tab, mlpw, s_ex->log);
+                const AT z = approx_rv<RV, DEG, AT, PREC>(r[0].w[i], s_tab, mlpw);
                 if constexpr (kKahan) {
                     em_step_kahan<SCHEME, AT>(Xfb, cfb, z, ca_b, cb_b, cm_b, one_b, rnd);
                     if (coarse) em_step_kahan<SCHEME, AT>(Xcb, ccb, rnd(zb_prev + z), cac_b, cb_b, cm_b, two_b, rnd);
@@ -305,8 +305,8 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
             if constexpr (kNeedApprox && PREC == MLMC_FP16) {
                 __half z0, z1;
                 if constexpr (RV == MLMC_RV_MLP) {
-                    z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw, s_ex->log));
-                    z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw, s_ex->log));
+                    z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw));
+                    z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw));
                 } else if constexpr (RV == MLMC_RV_PCONST4096) {
                     z0 = icdf_pconst_f16(r[0].w[i], s_tab16);
                     z1 = icdf_pconst_f16(r[1].w[i], s_tab16);
@@ -328,7 +328,7 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     double zt;
-                    if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw, s_ex->log);
+                    if constexpr (RV == MLMC_RV_MLP) zt = (double)icdf_mlp_f32(r[l].w[i], mlpw);
                     else if constexpr (RV == MLMC_RV_PCONST4096) zt = icdf_pconst_f64(r[l].w[i], s_tab64);
                     else zt = icdf_dyadic_f64<DEG>(r[l].w[i], s_tab64);
                     em_step<SCHEME, double>(Xft[l], zt, ca64, prm.cb_f64, prm.cm_f64, 1.0);
@@ -437,9 +437,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RV == MLMC_
     __shared__ __half s_tab16[kTab16 ? kTabN : 1];
     __shared__ double s_tab64[(kDyadic || kPconst) && DIAG ? kTabN : 1];
     __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
-    // the exact variable's top cells, and the log cells for the learned variable's input
-    constexpr size_t kExBytes = RV == MLMC_RV_MLP ? sizeof(ExactLds)
-                                : (RV == MLMC_RV_EXACT || NESTED) ? sizeof(ExactCols) : 0;
+    // the exact variable's top cells
+    constexpr size_t kExBytes = (RV == MLMC_RV_EXACT || NESTED) ? sizeof(ExactCols) : 0;
     __shared__ __align__(16) unsigned char s_ex_raw[kExBytes ? kExBytes : 16];
     const ExactLds* s_ex = (const ExactLds*)s_ex_raw;
     if constexpr (kExBytes > 0) {

@@ -1,14 +1,17 @@
-// The learned approximate inverse CDF: a 1-16-16-1 tanh network, device side.
+// The learned approximate inverse CDF: a 1-16-16-1 piecewise-linear network, device side.
 //
 // An approximate Gaussian variable in the sense of Section 2.1 / Assumption 2.1, mirrored
-// about u = 1/2 (exactly zero mean) and bounded for 32-bit words:
-//   u' = min(u, 1 - u), r = sqrt(-2 ln(2u')), x = r / 3.4 - 1,
-//   h1 = tanh(W1 x + b1), h2 = tanh(W2 h1 + b2), y = W3 . h2 + b3,
+// about u = 1/2 (exactly zero mean) and bounded for 32-bit words.  Deployed form (the
+// training form's hard tanh h = min(max(z, -1), 1) rewritten with c = (h + 1) / 2, so every
+// activation is the clamp to [0, 1] of the instruction that forms its argument):
+//   2u = R_32(2 xm + 1) 2^-32, r = sqrt(-2 ln 2u), x = R_16(r C - 1), C = R_32(1 / 3.4),
+//   c1 = clamp01(A1 x + a1)            (packed binary16 fused multiply-add, clamped),
+//   c2 = clamp01(A2 c1 + a2)           (binary16 matrix instruction, binary32 accumulation),
+//   y  = A3 . c2 + a3                  (binary32),
 //   Z~ = y - r (u < 1/2), r - y (u >= 1/2);
-// y learns the smooth residual Phi^{-1}(u') + r.  Inference uses the parameters rounded to
-// binary16 (staged in LDS widened to binary32) with binary32 arithmetic and accumulation, the
-// 16 x 16 layer as binary32 matrix instructions; r comes from the binary64 -log so that it
-// stays accurate next to u' = 1/2.
+// y learns the smooth residual Phi^{-1}(u') + r.  The parameters are binary16 values staged
+// in LDS widened to binary32; r uses the hardware base-2 logarithm and square root (no
+// binary64 work, no exponential or reciprocal per unit).
 #pragma once
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -25,74 +28,83 @@ constexpr float kMlpRScale = 3.4f;
 // offsets of the parameter blocks in the flat vector
 constexpr int kW1 = 0, kB1 = 16, kW2 = 32, kB2 = 288, kW3 = 304, kB3 = 320;
 
-__device__ __forceinline__ float tanh_fast(float a) {
-    // tanh(a) = 1 - 2 / (exp(2a) + 1), hardware base-2 exponential and reciprocal
-    const float e = __builtin_amdgcn_exp2f(a * 2.8853900817779268f);  // 2 / ln 2
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
-}
-
-// r = sqrt(-2 ln(2u')) for the mirrored word xm, u' = (xm + 1/2) 2^-32.
+// r = sqrt(-2 ln(2u')) in binary64 for the mirrored word xm, u' = (xm + 1/2) 2^-32 (the
+// input of the training pairs).
 __device__ __forceinline__ double mlp_radius(uint32_t xm, const LogCell* __restrict__ logtab) {
     const double two_u = ((double)xm + 0.5) * 0x1p-31;  // exact
     return __builtin_sqrt(2.0 * neg_log_f64(two_u, logtab));
 }
 
-// Network output for every lane's own input x, the 16 x 16 layer on the matrix cores.  W is
-// the binary32 image of the binary16 parameters (LDS or global memory).  All 64 lanes of
-// the wavefront must call it together (a matrix instruction works on the whole wave).
+typedef _Float16 mlp_h2 __attribute__((ext_vector_type(2)));
+typedef _Float16 mlp_h4 __attribute__((ext_vector_type(4)));
+typedef float mlp_f4 __attribute__((ext_vector_type(4)));
+
+// Two units of the first layer: one packed binary16 fused multiply-add, clamped to [0, 1]
+// (the compiler folds the clamp into the instruction's clamp modifier).  Written without
+// inline assembly so that the compiler sees the operands and keeps the wait states between
+// these instructions and the matrix instruction that reads them.
+__device__ __forceinline__ mlp_h2 mlp_unit_pair(mlp_h2 w, mlp_h2 x, mlp_h2 b) {
+    const mlp_h2 zero = {(_Float16)0.0f, (_Float16)0.0f}, one = {(_Float16)1.0f, (_Float16)1.0f};
+    return __builtin_elementwise_min(__builtin_elementwise_max(__builtin_elementwise_fma(w, x, b), zero), one);
+}
+__device__ __forceinline__ mlp_h2 mlp_pair(float lo, float hi) {
+    const mlp_h2 v = {(_Float16)lo, (_Float16)hi};  // exact: the image holds binary16 values
+    return v;
+}
+
+// Network output y for every lane's own binary16 input x16 (low half of x16x2, repeated in
+// the high half).  W is the binary32 image of the deployed binary16 parameters.  All 64
+// lanes of the wavefront must call it together (a matrix instruction works on the whole wave).
 //
-// Lanes are split as lane = 16 g + c.  For the samples of lanes 16 b + c (b = 0..3), lane
-// 16 g + c evaluates the hidden units 4 j + g of the first layer, which is the B operand of
-// v_mfma_f32_16x16x4_f32 (B[k][s] in lane 16 k + s) with A[n][k] = W2[n][4 j + k] (A[n][k]
-// in lane 16 k + n): four such products over j give out[n][s] for one block of 16 samples,
-// returned as D[n][s] = d[n % 4] in lane 16 (n / 4) + s.  Each lane then applies the second
-// tanh and the output weights to its four units n = 4 g .. 4 g + 3 of every block, the
-// partial sums are added over the four lane groups, and lane 16 g + c keeps block g: its own
-// sample.  The products and sums are binary32, as in the per-lane evaluation.
-__device__ __forceinline__ float mlp_eval_wave(float x, const float* __restrict__ W) {
-    typedef float v4f __attribute__((ext_vector_type(4)));
+// Lanes are split as lane = 16 g + c.  v_mfma_f32_16x16x16_f16 takes A[n][k] in lane
+// 16 (k / 4) + n, element k % 4, B[k][s] in lane 16 (k / 4) + s, and returns D[n][s] in lane
+// 16 (n / 4) + s, element n % 4.  For block b (the samples of lanes 16 b + c), lane 16 g + c
+// evaluates the first-layer units 4 g .. 4 g + 3 of sample 16 b + c (two packed fused
+// multiply-adds on that sample's input): the B operand.  A = A2, C = a2, so D holds the
+// second layer's arguments; each lane clamps its four units, weighs them with A3, and the
+// partial sums are added over the four lane groups (two lane-permutation swaps, no LDS), lane
+// 16 g + c keeping block g: its own sample.
+__device__ __forceinline__ float mlp_eval_wave(uint32_t x16x2, const float* __restrict__ W) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t c = lane & 15u, g = lane >> 4;
-    float w1[4], b1[4], w2[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t k = 4u * j + g;
-        w1[j] = W[kW1 + k];
-        b1[j] = W[kB1 + k];
-        w2[j] = W[kW2 + c * kMlpHidden + k];
-    }
+    const uint32_t k0 = 4u * g;
+    const mlp_h2 w1a = mlp_pair(W[kW1 + k0], W[kW1 + k0 + 1]), w1b = mlp_pair(W[kW1 + k0 + 2], W[kW1 + k0 + 3]);
+    const mlp_h2 b1a = mlp_pair(W[kB1 + k0], W[kB1 + k0 + 1]), b1b = mlp_pair(W[kB1 + k0 + 2], W[kB1 + k0 + 3]);
+    const mlp_h4 w2 = {(_Float16)W[kW2 + c * kMlpHidden + k0], (_Float16)W[kW2 + c * kMlpHidden + k0 + 1],
+                       (_Float16)W[kW2 + c * kMlpHidden + k0 + 2], (_Float16)W[kW2 + c * kMlpHidden + k0 + 3]};
+    const mlp_f4 b2 = {W[kB2 + k0], W[kB2 + k0 + 1], W[kB2 + k0 + 2], W[kB2 + k0 + 3]};
     float part[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const float xb = __shfl(x, 16 * b + (int)c, kWave);
-        v4f d = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            d = __builtin_amdgcn_mfma_f32_16x16x4f32(w2[j], tanh_fast(__builtin_fmaf(w1[j], xb, b1[j])), d, 0, 0, 0);
+        const mlp_h2 xb = __builtin_bit_cast(mlp_h2, (uint32_t)__shfl((int)x16x2, 16 * b + (int)c, kWave));
+        const mlp_h2 h01 = mlp_unit_pair(w1a, xb, b1a), h23 = mlp_unit_pair(w1b, xb, b1b);
+        const mlp_h4 bop = {h01[0], h01[1], h23[0], h23[1]};
+        const mlp_f4 d = __builtin_amdgcn_mfma_f32_16x16x16f16(w2, bop, b2, 0, 0, 0);
         float p = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t n = 4u * g + r;
-            p = __builtin_fmaf(W[kW3 + n], tanh_fast(d[r] + W[kB2 + n]), p);
-        }
+        for (int r = 0; r < 4; ++r)
+            p = __builtin_fmaf(W[kW3 + k0 + r], __builtin_amdgcn_fmed3f(d[r], 0.0f, 1.0f), p);
         part[b] = p;
     }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        part[b] += __shfl_xor(part[b], 16, kWave);
-        part[b] += __shfl_xor(part[b], 32, kWave);
-    }
-    const float y = g == 0 ? part[0] : g == 1 ? part[1] : g == 2 ? part[2] : part[3];
-    return y + W[kB3];
+    // sum over the four lane groups, each lane keeping its own block: swapping the lane halves
+    // pairs block 0 with 2 and 1 with 3 (lanes 0..31 keep blocks 0, 1), swapping odd and even
+    // rows of 16 lanes leaves row g with block g
+    const auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[0]), __float_as_uint(part[2]), false, false);
+    const auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[1]), __float_as_uint(part[3]), false, false);
+    const float q0 = __uint_as_float(s02[0]) + __uint_as_float(s02[1]);
+    const float q1 = __uint_as_float(s13[0]) + __uint_as_float(s13[1]);
+    const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(q0), __float_as_uint(q1), false, false);
+    return (__uint_as_float(t[0]) + __uint_as_float(t[1])) + W[kB3];
 }
 
 // The learned approximate variable of every lane's word (all 64 lanes together).
-__device__ __forceinline__ float icdf_mlp_f32(uint32_t word, const float* __restrict__ W,
-                                              const LogCell* __restrict__ logtab) {
+__device__ __forceinline__ float icdf_mlp_f32(uint32_t word, const float* __restrict__ W) {
     const uint32_t xm = word ^ (uint32_t)((int32_t)word >> 31);  // ~word on the upper half
-    const double r = mlp_radius(xm, logtab);
-    const float x = (float)(r * (1.0 / 3.4) - 1.0);
-    const float q = mlp_eval_wave(x, W) - (float)r;
+    const float two_u = (float)(2u * xm + 1u) * 0x1p-32f;         // R_32(2 xm + 1), scaled exactly
+    const float r = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(two_u) * -1.38629436111989061f);  // -2 ln 2
+    const float x = __builtin_fmaf(r, (float)(1.0 / 3.4), -1.0f);
+    const uint32_t x16 = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
+    const float q = mlp_eval_wave(x16 | (x16 << 16), W) - r;
     return apply_sign(q, word & 0x80000000u);
 }
 

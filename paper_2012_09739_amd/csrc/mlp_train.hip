@@ -4,9 +4,10 @@
 // Pairs (Philox stream 2): pair i draws words w0, w1 of counter (0, i, 2 << 16, 0); even
 // pairs are uniform (w0 mirrored to the lower half), odd pairs tail-weighted
 // (xm = (w0 >> 1) >> (w1 mod 31)).  Input x = r / 3.4 - 1 and target Phi^{-1}(u') + r with
-// the binary64 exact inverse.  Loss: mean squared error over a mini-batch.  Every sum
-// (per-block gradient, across blocks) is taken in a fixed order, so training is
-// bit-reproducible.
+// the binary64 exact inverse.  The trained network uses the hard tanh min(max(z, -1), 1)
+// (slope 1 inside, 0 outside); deployment rewrites it with clamps to [0, 1] (mlp.h).  Loss:
+// mean squared error over a mini-batch.  Every sum (per-block gradient, across blocks) is
+// taken in a fixed order, so training is bit-reproducible.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,6 +26,10 @@ namespace {
 constexpr int kTB = 128;          // samples per training block
 constexpr int kGradStride = 324;  // 321 gradients + loss, padded
 constexpr float kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
+
+__device__ __forceinline__ float hard_tanh(float z) { return fminf(fmaxf(z, -1.0f), 1.0f); }
+// slope of the hard tanh at its argument z, from its value h = hard_tanh(z): 1 inside (-1, 1)
+__device__ __forceinline__ float hard_tanh_slope(float h) { return (h > -1.0f && h < 1.0f) ? 1.0f : 0.0f; }
 
 __device__ __forceinline__ uint32_t pair_word(uint32_t i, uint32_t k0, uint32_t k1) {
     const Words4 r = philox4x32_10(0u, i, 2u << 16, 0u, k0, k1);
@@ -61,7 +66,7 @@ __global__ __launch_bounds__(kTB) void grad_kernel(const float* __restrict__ par
     const float target = valid ? ts[i] : 0.0f;
     float h1[kMlpHidden], h2[kMlpHidden];
 #pragma unroll
-    for (int k = 0; k < kMlpHidden; ++k) h1[k] = tanh_fast(__builtin_fmaf(sW[kW1 + k], x, sW[kB1 + k]));
+    for (int k = 0; k < kMlpHidden; ++k) h1[k] = hard_tanh(__builtin_fmaf(sW[kW1 + k], x, sW[kB1 + k]));
     float y = sW[kB3];
 #pragma unroll
     for (int k = 0; k < kMlpHidden; ++k) {
@@ -69,7 +74,7 @@ __global__ __launch_bounds__(kTB) void grad_kernel(const float* __restrict__ par
         float a = sW[kB2 + k];
 #pragma unroll
         for (int j = 0; j < kMlpHidden; ++j) a = __builtin_fmaf(sW[kW2 + k * kMlpHidden + j], h1[j], a);
-        h2[k] = tanh_fast(a);
+        h2[k] = hard_tanh(a);
         y = __builtin_fmaf(sW[kW3 + k], h2[k], y);
     }
     const float res = valid ? y - target : 0.0f;
@@ -80,7 +85,7 @@ __global__ __launch_bounds__(kTB) void grad_kernel(const float* __restrict__ par
 #pragma unroll
     for (int k = 0; k < kMlpHidden; ++k) {
         asm volatile("" ::: "memory");
-        const float da2 = dy * sW[kW3 + k] * (1.0f - h2[k] * h2[k]);
+        const float da2 = dy * sW[kW3 + k] * hard_tanh_slope(h2[k]);
         s_da2[k][t] = da2;
         s_h2[k][t] = h2[k];
 #pragma unroll
@@ -89,7 +94,7 @@ __global__ __launch_bounds__(kTB) void grad_kernel(const float* __restrict__ par
 #pragma unroll
     for (int j = 0; j < kMlpHidden; ++j) {
         s_h1[j][t] = h1[j];
-        s_da1[j][t] = dh1[j] * (1.0f - h1[j] * h1[j]);
+        s_da1[j][t] = dh1[j] * hard_tanh_slope(h1[j]);
     }
     s_x[t] = x;
     s_dy[t] = dy;
@@ -167,10 +172,33 @@ __global__ void fill_kernel(float* __restrict__ p, uint32_t n, float v, uint32_t
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) counter[0] = 0u;
 }
 
-// Inference image: round each parameter once to binary16, store it widened to binary32.
+// Inference image: the deployed form of the parameters (c = (h + 1) / 2 for every hard-tanh
+// unit h), A1 = W1 / 2, a1 = (b1 + 1) / 2, A2 = W2, a2 = (b2 - W2 1 + 1) / 2, A3 = 2 W3,
+// a3 = b3 - W3 . 1, each formed in binary32 (sums in index order), rounded once to binary16
+// and stored widened to binary32.
 __global__ void deploy_kernel(const float* __restrict__ params, float* __restrict__ image) {
     const int i = threadIdx.x;
-    if (i < kMlpImage) image[i] = i < kMlpParams ? __half2float(__float2half_rn(params[i])) : 0.0f;
+    if (i >= kMlpImage) return;
+    float v = 0.0f;
+    if (i < kB1) {
+        v = params[i] * 0.5f;
+    } else if (i < kW2) {
+        v = (params[i] + 1.0f) * 0.5f;
+    } else if (i < kB2) {
+        v = params[i];
+    } else if (i < kW3) {
+        const int n = i - kB2;
+        float s = 0.0f;
+        for (int k = 0; k < kMlpHidden; ++k) s = __fadd_rn(s, params[kW2 + n * kMlpHidden + k]);
+        v = __fmul_rn(__fadd_rn(__fadd_rn(params[i], -s), 1.0f), 0.5f);
+    } else if (i < kB3) {
+        v = params[i] * 2.0f;
+    } else if (i == kB3) {
+        float s = 0.0f;
+        for (int k = 0; k < kMlpHidden; ++k) s = __fadd_rn(s, params[kW3 + k]);
+        v = __fadd_rn(params[i], -s);
+    }
+    image[i] = i < kMlpParams ? __half2float(__float2half_rn(v)) : 0.0f;
 }
 
 int ck(hipError_t e, const char* what) {

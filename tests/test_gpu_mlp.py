@@ -1,6 +1,7 @@
 """GPU tests of the learned approximate inverse CDF: training pairs, gradients and the Adam
 step against the float64 oracle, inference parity on seeded weights, and what the trained
-network gains over the piecewise-linear table (approximation error and four-way variance)."""
+network gains over the piecewise-linear table (approximation error, four-way variance and
+the equal-variance time of the nested estimator)."""
 
 import numpy as np
 import pytest
@@ -74,19 +75,31 @@ def test_first_adam_step_matches_oracle():
     assert np.all(np.abs(got - p32) <= 1e-3 * 1.001)
 
 
+# bound on |x_gpu - x| for the network input before its binary16 rounding: r from the
+# hardware base-2 logarithm and square root within a few binary32 ulps (r <= 6.7), times
+# C = 0.294, plus the binary32 rounding of r C - 1
+FEATURE_DELTA = 1e-6
+
+
 def test_inference_matches_oracle_on_seeded_weights():
+    """The learned variable against the oracle's deployed model.  Where the network input
+    r C - 1 lies within FEATURE_DELTA of a binary16 rounding boundary, either rounding of it
+    is a correct binary16 input; the variable must then match the oracle for one of the two."""
     torch = torch_cuda()
     p = W.mlp_initial_params(5) + np.random.default_rng(6).normal(0, 0.1, mlp.N_PARAMS)
     M.mlmc_mlp_load(dev(p))
     rng = np.random.default_rng(9)
     words = np.concatenate([rng.integers(0, 2 ** 32, 20000, dtype=np.uint64),
                             np.array([0, 1, 2 ** 31 - 1, 2 ** 31, 2 ** 32 - 1], dtype=np.uint64)])
-    p16 = mlp.deployed(p.astype(np.float32))
+    q = mlp.deployed(p.astype(np.float32))
+    lo, hi = mlp.input16_neighbours(words, FEATURE_DELTA)
+    assert np.mean(lo != hi) < 0.01
+    want = [mlp.approx_icdf(words, q, fp.FP64, x16=x16) for x16 in (lo, hi)]
     for prec in (M.MLMC_FP64, M.MLMC_FP32, M.MLMC_FP16):
         got = gpu_icdf(words, M.MLMC_RV_MLP, prec)
-        want = mlp.approx_icdf(words, p16, fp.FP64)
         tol = 1e-5 if prec != M.MLMC_FP16 else 4e-3
-        assert np.max(np.abs(got - want)) <= tol, prec
+        ok = (np.abs(got - want[0]) <= tol) | (np.abs(got - want[1]) <= tol)
+        assert np.all(ok), (prec, words[~ok][:5], got[~ok][:5], want[0][~ok][:5])
     zm = gpu_icdf(np.uint64(2 ** 32 - 1) - words, M.MLMC_RV_MLP, M.MLMC_FP32)
     np.testing.assert_array_equal(zm, -gpu_icdf(words, M.MLMC_RV_MLP, M.MLMC_FP32))
 
@@ -95,11 +108,11 @@ def test_nested_mlp_paths_match_oracle():
     torch = torch_cuda()
     p = W.mlp_initial_params(5) + np.random.default_rng(6).normal(0, 0.1, mlp.N_PARAMS)
     M.mlmc_mlp_load(dev(p))
-    p16 = mlp.deployed(p.astype(np.float32))
+    q = mlp.deployed(p.astype(np.float32))
     n, level = 1000, 4
     g = gpu_paths(W.GBM_CALL, level, n, M.MLMC_FP32, M.MLMC_RV_MLP, True, 1, 8)
     o = mlmc.level_paths(level, np.arange(n), W.GBM_CALL, rv_mode=mlmc.RV_MLP, precision=fp.FP32, nested=True,
-                         kahan=True, seed=8, stream=1, mlp_params=p16)
+                         kahan=True, seed=8, stream=1, mlp_params=q)
     assert np.max(np.abs(g["pf_hat"] - o["Pf_hat"])) <= 1e-13
     assert np.all(close(g["pf_bar"], o["Pf_bar"], 1e-5))
     assert np.all(close(g["pc_bar"], o["Pc_bar"], 1e-5))

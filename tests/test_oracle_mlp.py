@@ -1,14 +1,18 @@
 """Pins of the oracle's MLP surrogate: gradients vs central finite differences, Adam vs its
-closed form under a constant gradient, and exact mirror symmetry of the deployed model."""
+closed form under a constant gradient, the deployed (clamp to [0, 1]) form equal to the
+training (hard tanh) form in exact arithmetic, and exact mirror symmetry of the deployed
+model."""
 
 import numpy as np
+import pytest
 
 from oracle import fp, mlp
 
 
 def _params(seed=0):
+    # weights large enough that every unit saturates somewhere on the inputs used
     rng = np.random.default_rng(seed)
-    return rng.normal(0, 0.5, mlp.N_PARAMS)
+    return rng.normal(0, 1.5, mlp.N_PARAMS)
 
 
 def test_backprop_matches_finite_differences():
@@ -40,15 +44,63 @@ def test_adam_closed_form_constant_gradient():
         np.testing.assert_allclose(p, p0 - t * lr * g / (np.abs(g) + mlp.ADAM_EPS), rtol=1e-12)
 
 
+def test_hard_tanh_and_its_slope():
+    z = np.array([-3.0, -1.0, -0.25, 0.0, 0.5, 1.0, 2.0])
+    np.testing.assert_array_equal(mlp.hard_tanh(z), [-1.0, -1.0, -0.25, 0.0, 0.5, 1.0, 1.0])
+    np.testing.assert_array_equal(mlp.hard_tanh_slope(z), [0, 0, 1, 1, 1, 0, 0])
+
+
+def test_backprop_of_a_unit_in_its_linear_region():
+    # one hidden path in the linear region: y = W3[0] (W2[0,0] (W1[0] x + b1[0]) + b2[0]) + b3
+    p = np.zeros(mlp.N_PARAMS)
+    W1, b1, W2, b2, W3, b3 = (0.5, 0.1, 0.8, -0.2, 1.5, 0.3)
+    p[0], p[16], p[32], p[288], p[304], p[320] = W1, b1, W2, b2, W3, b3
+    x = np.array([0.4])
+    h1 = W1 * 0.4 + b1
+    y = W3 * (W2 * h1 + b2) + b3
+    got, _ = mlp.forward(p, x)
+    assert got[0] == pytest.approx(y, rel=1e-15)
+    _, g = mlp.loss_grad(p, x, np.array([0.0]))
+    dy = 2.0 * y
+    assert g[320] == pytest.approx(dy) and g[304] == pytest.approx(dy * (W2 * h1 + b2))
+    assert g[32] == pytest.approx(dy * W3 * h1) and g[0] == pytest.approx(dy * W3 * W2 * 0.4)
+
+
+def test_deployed_form_equals_training_form_without_rounding():
+    # c = (h + 1) / 2: the folded parameters give the same y in exact arithmetic
+    p = _params(4)
+    q = mlp.fold(p, rounding=np.float64)
+    x = np.linspace(-1.0, 1.0, 4001)
+    y, _ = mlp.forward(p, x)
+    A1, a1, A2, a2, A3, a3 = mlp.unpack(q)
+    c1 = np.clip(np.outer(x, A1) + a1, 0.0, 1.0)
+    c2 = np.clip(c1 @ A2.T + a2, 0.0, 1.0)
+    np.testing.assert_allclose(c2 @ A3 + a3, y, rtol=0, atol=1e-12)
+    # the binary32 fold agrees with the float64 one to binary32 rounding
+    np.testing.assert_allclose(mlp.fold(p), q, rtol=1e-5, atol=1e-5)
+
+
 def test_deployed_model_is_mirror_symmetric_and_bounded():
-    p16 = mlp.deployed(_params(3))
+    q = mlp.deployed(_params(3))
+    assert np.all(q.astype(np.float16).astype(np.float64) == q)     # binary16 values
     x = np.random.default_rng(2).integers(0, 2 ** 32, 5000, dtype=np.uint64)
-    z = mlp.approx_icdf(x, p16, fp.FP64)
-    zm = mlp.approx_icdf(np.uint64(2 ** 32 - 1) - x, p16, fp.FP64)
+    z = mlp.approx_icdf(x, q, fp.FP64)
+    zm = mlp.approx_icdf(np.uint64(2 ** 32 - 1) - x, q, fp.FP64)
     np.testing.assert_array_equal(zm, -z)
-    W1, b1, W2, b2, W3, b3 = mlp.unpack(p16)
-    # |Z~| <= r + |y| with r <= sqrt(64 ln 2) for 32-bit words
-    assert np.abs(z).max() <= np.sqrt(64 * np.log(2.0)) + abs(b3) + np.abs(W3).sum()
+    A1, a1, A2, a2, A3, a3 = mlp.unpack(q)
+    # |Z~| <= r + |y| with r <= sqrt(64 ln 2) for 32-bit words and c2 in [0, 1]
+    assert np.abs(z).max() <= np.sqrt(64 * np.log(2.0)) + abs(a3) + np.abs(A3).sum()
+
+
+def test_inference_input_and_radius():
+    # 2u'' = R_32(2 xm + 1) 2^-32: word 0 gives 2^-32 exactly, the middle word rounds to 1
+    r, two_u = mlp.radius(np.array([0, 2 ** 31 - 1], dtype=np.uint64))
+    assert two_u[0] == 2.0 ** -32 and two_u[1] == 1.0 and r[1] == 0.0
+    assert r[0] == pytest.approx(np.sqrt(64 * np.log(2.0)), rel=1e-15)
+    x16 = mlp.input16(r)
+    assert x16[1] == -1.0 and np.float16(x16[0]) == x16[0]
+    lo, hi = mlp.input16_neighbours(np.array([0, 12345, 2 ** 31 - 1], dtype=np.uint64), 0.0)
+    np.testing.assert_array_equal(lo, hi)
 
 
 def test_feature_range():
