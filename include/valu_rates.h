@@ -41,6 +41,21 @@ enum {
     VALU_MAD_U64_U32,  /* 32 x 32 -> 64 integer product with 64-bit addend */
     VALU_CVT_F64_F32,  /* v_cvt_f32_f64 + v_cvt_f64_f32 (rate per instruction) */
     VALU_CVT_F16_F32,  /* v_cvt_f16_f32 + v_cvt_f32_f16 (rate per instruction) */
+    VALU_MIN_U32,
+    VALU_LSHL_OR_B32,
+    VALU_CNDMASK_B32,  /* v_cmp_gt_u32 + v_cndmask_b32 (rate per instruction) */
+    VALU_PERM_B32,
+    VALU_AND_B32,
+    VALU_ASHR_I32,
+    VALU_ADD_F16,      /* scalar binary16 */
+    VALU_MUL_F16,      /* scalar binary16 */
+    VALU_PK_ADD_F16,
+    VALU_CVT_PK_F16_F32,
+    VALU_CVT_F32_U32,
+    VALU_CVT_F64_U32,
+    VALU_LSHL_B64,
+    VALU_LSHL_ADD_U64,
+    VALU_MOV_B64,
     VALU_N_OPS
 };
 

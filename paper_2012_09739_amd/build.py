@@ -84,5 +84,58 @@ def build(verbose=False, jobs=None):
     return LIB
 
 
+# Host sanitizers: the host side of every translation unit (argument validation, tables,
+# launch code) with AddressSanitizer and UndefinedBehaviorSanitizer, the device code as
+# usual; for the CPU tests of the C-ABI (tests/test_abi.py), loaded through MLMC_LIBRARY with
+# the sanitizer runtime preloaded into the interpreter.
+SANITIZED_LIB = os.path.join(BUILD, "libmlmc_sanitized.so")
+_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+        "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-shared-libasan"]
+
+
+def sanitizer_runtime():
+    """Path of the AddressSanitizer runtime of the HIP compiler (to LD_PRELOAD)."""
+    r = subprocess.run([os.path.join(os.path.dirname(os.path.realpath(_clangxx())), "clang++"),
+                        "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("AddressSanitizer runtime not found")
+    return path
+
+
+def _clangxx():
+    for cand in ("/opt/rocm/llvm/bin/clang++", "/opt/rocm/lib/llvm/bin/clang++"):
+        if os.path.exists(cand):
+            return cand
+    return "clang++"
+
+
+def build_sanitized(verbose=False, jobs=None):
+    """libmlmc with host sanitizers (in the build folder, not the product library)."""
+    os.makedirs(BUILD, exist_ok=True)
+    hipcc = _hipcc()
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    cmds, objs = [], []
+    for src in HIP_SOURCES:
+        obj = os.path.join(BUILD, "san_" + src.replace(".", "_") + ".o")
+        cmds.append([hipcc, "-c", *COMMON, *HIP_FLAGS, *EXTRA_FLAGS.get(src, []), *_SAN, os.path.join(CSRC, src),
+                     "-o", obj])
+        objs.append(obj)
+    for src in CXX_SOURCES:
+        obj = os.path.join(BUILD, "san_" + src.replace(".", "_") + ".o")
+        cmds.append([_clangxx(), "-c", *COMMON, "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                     "-fno-omit-frame-pointer", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *_SAN, "-o", SANITIZED_LIB, *objs], verbose)
+    return SANITIZED_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+        print(sanitizer_runtime())
+    else:
+        print(build(verbose="-v" in sys.argv))

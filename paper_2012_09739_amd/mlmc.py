@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmlmc.so")
+# MLMC_LIBRARY selects another build of the same library (the host-sanitizer build of the
+# CPU tests); by default the in-tree libmlmc.so
+LIB_PATH = os.environ.get("MLMC_LIBRARY") or os.path.join(HERE, "libmlmc.so")
 
 MLMC_OK, MLMC_EINVAL, MLMC_ENOMEM, MLMC_ENODEV, MLMC_EHIP, MLMC_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MLMC_FP64, MLMC_FP32, MLMC_FP16 = 0, 1, 2
