@@ -101,7 +101,9 @@ VALU_OPS = ("v_fma_f64", "v_mul_f64", "v_add_f64", "v_fma_f32", "v_mul_f32", "v_
             "v_exp_f32", "v_rcp_f32", "v_med3_f32", "v_mad_u64_u32", "v_cvt_f32_f64 + v_cvt_f64_f32",
             "v_cvt_f16_f32 + v_cvt_f32_f16", "v_min_u32", "v_lshl_or_b32", "v_cmp_gt_u32 + v_cndmask_b32",
             "v_perm_b32", "v_and_b32", "v_ashrrev_i32", "v_add_f16", "v_mul_f16", "v_pk_add_f16", "v_cvt_pk_f16_f32",
-            "v_cvt_f32_u32", "v_cvt_f64_u32", "v_lshlrev_b64", "v_lshl_add_u64", "v_mov_b64")
+            "v_cvt_f32_u32", "v_cvt_f64_u32", "v_lshlrev_b64", "v_lshl_add_u64", "v_mov_b64",
+            "v_max_f32 clamp", "v_sub_u32 clamp", "v_lshrrev_b32", "v_fma_mixlo_f16", "v_bitop3_b16", "v_log_f32",
+            "v_sqrt_f32", "v_cmp_gt_u32")
 
 
 def parse():
@@ -117,6 +119,9 @@ def parse():
                    help="comma-separated report legs to run: " + ", ".join(REPORT_LEGS))
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a device copy of known size (HBM counter calibration)")
+    p.add_argument("--profile", choices=("roofline", "valu_rates"),
+                   help="profiling run: only the dominant kernels' timed launches (roofline) or only "
+                        "the issue-rate probes, printed as one JSON line without the headline metric")
     return p.parse_args()
 
 
@@ -127,6 +132,9 @@ def main():
               "paths shard across GPUs by path_offset but no multi-GPU run is made",
               file=sys.stderr)
         sys.exit(2)
+    if a.profile:
+        profile_run(a.profile, a.calibrate_copy)
+        return
     # the CPU oracle runs first, in worker processes started before anything touches the GPU
     cpu = None if a.no_cpu_baseline else cpu_baseline()
 
@@ -220,7 +228,66 @@ def main():
         "roofline_fp16": roof["fp16"],
         "cpu_baseline": cpu,
     }
+    line["speedup_equal_variance"] = equal_variance_summary(extra)
     line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def equal_variance_summary(extra):
+    """T^ / T- (plain binary64 time over nested time at equal total MLMC variance, Section 3)
+    of every configuration the run measured, gathered at the top level of the line."""
+    out = {}
+    ev = extra.get("equal_variance", {})
+    for tag, key in (("fp32_pwl16_levels0to10", "fp32"), ("fp32_pwl16_kahan_levels0to10", "fp32_kahan")):
+        if key in ev:
+            out[tag] = ev[key]["speedup_T_hat_over_T_bar"]
+    rep = extra.get("reports", {})
+    f16 = rep.get("nested_fp16_cubic16_kahan_levels0to6_2p24")
+    if f16:
+        out["fp16_cubic16_kahan_levels0to6"] = f16["speedup_T_hat_over_T_bar"]
+    pc = rep.get("pconst4096_vs_dyadic_call_levels0to10_2p20")
+    if pc:
+        out["fp16_cubic16_kahan_levels0to10"] = pc["fp16_cubic16_kahan"]["speedup_T_hat_over_T_bar"]
+        out["fp32_pconst4096_levels0to10"] = pc["fp32_pconst"]["speedup_T_hat_over_T_bar"]
+        out["fp16_pconst4096_kahan_levels0to10"] = pc["fp16_pconst_kahan"]["speedup_T_hat_over_T_bar"]
+    mlp = rep.get("mlp_nested_fp32_levels0to10_2p22")
+    if mlp:
+        out["fp32_mlp_levels0to10"] = mlp["speedup_T_hat_over_T_bar"]["mlp"]
+    return out
+
+
+def profile_run(what, calibrate_copy):
+    """The launches a rocprofv3 summary of the roofline numbers covers: the dominant kernels
+    exactly as roofline_block times them (2 warm-up and 10 timed launches each, nothing else
+    on the device), or the issue-rate probes."""
+    import torch
+
+    import paper_2012_09739_amd as M
+    torch.cuda.set_device(0)
+    M.mlmc_init(0)
+    line = {"profile": what}
+    if what == "roofline":
+        # the timed launches follow about a second of the same kind of load (the kernel's
+        # instance without Kahan updates, a separate entry in a profiler's statistics), as in
+        # the full run, where they follow the headline sweep: the shader clock settles first
+        call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
+        warm = M.level_args(call, 10, N_PATHS, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, SEED)
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 1.0:
+            for _ in range(50):
+                M.mlmc_paths(warm)
+            torch.cuda.synchronize()
+        for key in ROOFLINE_KERNELS:
+            line["roofline" if key == "fp32" else "roofline_" + key] = roofline_block(M, torch, key)
+        if calibrate_copy:
+            src = torch.empty(256 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            line["copy_calibration_bytes"] = 2 * src.numel() * 4
+    else:
+        line["valu_issue_rates"] = valu_rates()
     print(json.dumps(line), flush=True)
 
 
@@ -346,20 +413,28 @@ def reports(M, E, torch, legs=REPORT_LEGS):
     if "fp16" in legs:
         # packed binary16 with Kahan, piecewise cubic, binary64 exact branch: levels 0..6, 2^24 paths
         c3 = W.NESTED_FP16
-        nested16 = []
-        for l in c3["levels"]:
-            args = M.level_args(call, l, c3["n_paths"], M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1, SEED, diag=1)
-            out = torch.zeros(8, dtype=torch.float64, device="cuda")
-            M.mlmc_level_ex(args, out)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            M.mlmc_level_ex(args, out)
-            e1.record()
-            torch.cuda.synchronize()
-            o = out.cpu().numpy()
-            nested16.append({"sum": list(o[:4]), "sumsq": list(o[4:]), "n_paths": c3["n_paths"],
+
+        def nested_fp16(diag):
+            rows = []
+            for l in c3["levels"]:
+                args = M.level_args(call, l, c3["n_paths"], M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1, SEED, diag=diag)
+                out = torch.zeros(8, dtype=torch.float64, device="cuda")
+                M.mlmc_level_ex(args, out)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                M.mlmc_level_ex(args, out)
+                e1.record()
+                torch.cuda.synchronize()
+                o = out.cpu().numpy()
+                rows.append({"sum": list(o[:4]), "sumsq": list(o[4:]), "n_paths": c3["n_paths"],
                              "path_steps": c3["n_paths"] << l, "cost_seconds": e0.elapsed_time(e1) * 1e-3})
+            return rows
+
+        # the estimator's samples without the rounding diagnostic (its own binary64 path), and
+        # the diagnostic run for the rounding-difference variance
+        nested16 = nested_fp16(0)
+        diag16 = nested_fp16(1)
         plain = _level_costs(M, call, c3["levels"], c3["n_paths"], M.MLMC_FP64, M.MLMC_EXACT, 0)
         approx16 = _level_costs(M, call, c3["levels"], c3["n_paths"], M.MLMC_FP16, M.MLMC_APPROX_CUBIC16, 1)
         rho = 2.0 ** -11
@@ -368,7 +443,8 @@ def reports(M, E, torch, legs=REPORT_LEGS):
         rep["nested_fp16_cubic16_kahan_levels0to6_2p24"] = {
             "nested_path_steps_per_s": rate(nested16), "approx_two_way_path_steps_per_s": rate(approx16),
             "plain_fp64_path_steps_per_s": rate(plain),
-            "rounding_variance": var(nested16, 3), "rounding_variance_bound_B_l": bound,
+            "nested_with_rounding_diagnostic_path_steps_per_s": rate(diag16),
+            "rounding_variance": var(diag16, 3), "rounding_variance_bound_B_l": bound,
             "four_way_var": var(nested16, 1), "two_way_exact_var": var(nested16, 2),
             "speedup_T_hat_over_T_bar": E.speedup_equal_variance(var(plain, 0), cost(plain), var(approx16, 0),
                                                                  cost(approx16), var(nested16, 1), cost(nested16))}
@@ -406,9 +482,19 @@ def reports(M, E, torch, legs=REPORT_LEGS):
         per_level = {}
         for it, c in zip(items, share):
             per_level.setdefault(it.level, []).append(c / it.n_paths)
+        # the same work as one standalone level call per level (all parameter sets' paths in
+        # one launch: the drift and volatility do not change a path's cost), device times
+        stand = []
+        for l in W.BATCH_LEVELS:
+            prec = M.MLMC_FP16 if l <= 6 else M.MLMC_FP32
+            r = _level_costs(M, M.gbm(), [l], len(psets) * W.batch_paths(l), prec, M.MLMC_NESTED_PWL16,
+                             1 if prec == M.MLMC_FP16 else 0)[0]
+            stand.append(r["cost_seconds"] * 1e3)
         rep["batch_64psets_levels0to14"] = {
             "items": len(items), "tasks": n_tasks, "ms_per_sweep": ms, "path_steps": steps,
             "path_steps_per_s": steps / ms * 1e3,
+            "standalone_same_work_ms": sum(stand), "standalone_ms_by_level": stand,
+            "rate_over_standalone": sum(stand) / ms,
             "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level],
             "wave_slot_utilisation": sum(wave_s) / (resident * ms * 1e-3),
             "cost_per_sample_s_by_level": [float(np.mean(per_level[l])) for l in sorted(per_level)]}
@@ -608,11 +694,22 @@ def cpu_baseline():
         steps = sum(pool.imap_unordered(_oracle_task, tasks, chunksize=1))
         dt = time.perf_counter() - t0
     return {"value": steps / dt, "unit": "coupled path-steps/s", "cores": workers, "kind": "oracle",
-            "single_core_value": steps1 / dt1,
-            "sample": "nested binary32 PWL16 with Kahan, levels 0..10: %d worker processes on 2^%d paths/level "
-                      "(%d coupled path-steps, %.1f s) and one process on 2^%d paths/level (%d, %.1f s); "
-                      "NumPy oracle" % (workers, CPU_POOL_PATHS.bit_length() - 1, steps, dt,
-                                        CPU_SINGLE_PATHS.bit_length() - 1, steps1, dt1)}
+            "sample": "nested fp32 PWL16 Kahan, levels 0..10, 2^%d paths/level" % (CPU_POOL_PATHS.bit_length() - 1),
+            "sample_path_steps": steps, "sample_seconds": dt,
+            "single_core_value": steps1 / dt1, "single_core_sample_paths_per_level": CPU_SINGLE_PATHS,
+            "single_core_seconds": dt1, "host_cpu_count": os.cpu_count(), "host_cpu_model": _cpu_model(),
+            "worker_cap": CPU_MAX_WORKERS}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -56,6 +56,14 @@ enum {
     VALU_LSHL_B64,
     VALU_LSHL_ADD_U64,
     VALU_MOV_B64,
+    VALU_MAX_F32_CLAMP, /* v_max_f32 with the clamp modifier (a clamp to [0, 1]) */
+    VALU_SUB_U32_CLAMP, /* saturating 32-bit subtract */
+    VALU_LSHR_B32,
+    VALU_FMA_MIX_F16,   /* v_fma_mixlo_f16: binary32 operands, binary16 result */
+    VALU_BITOP3_B16,
+    VALU_LOG_F32,       /* transcendental unit */
+    VALU_SQRT_F32,      /* transcendental unit */
+    VALU_CMP_U32,       /* v_cmp_gt_u32 into a scalar register pair (no select) */
     VALU_N_OPS
 };
 

@@ -129,6 +129,26 @@ def _paths(level, Z, Zc_sum, consts, kahan, scheme=SCHEME_EM):
     return Xf, Xc
 
 
+def _mlp_payoff_allowance(level, Zt, allow, consts, Xf, Xc):
+    """Bounds on |P(X_N)| changes of the fine and the coarse path when each learned variable
+    Z~_n may move by allow_n (the two correct binary16 roundings of a second-layer sum).
+
+    Euler-Maruyama for GBM multiplies the state by f_n = 1 + ca + cb Z~_n per step, so to first
+    order dX_N / dZ~_n = cb X_N / f_n (coarse: the pair sum enters once, with the coarse
+    factor); the payoffs are 1-Lipschitz.  A factor 1.5 covers the second-order terms and the
+    rounding of the perturbed path (allow_n cb is below 1e-3 here)."""
+    ca_f, ca_c, cb = (float(consts[0]), float(consts[1]), float(consts[2]))
+    Zt = fp.to64(Zt)
+    ff = 1.0 + ca_f + cb * Zt
+    fine = cb * np.abs(Xf) * np.sum(allow / np.abs(ff), axis=1)
+    if level == 0:
+        return 1.5 * fine, np.zeros_like(fine)
+    Zc = Zt[:, 0::2] + Zt[:, 1::2]
+    fc = np.repeat(1.0 + ca_c + cb * Zc, 2, axis=1)
+    coarse = cb * np.abs(Xc) * np.sum(allow / np.abs(fc), axis=1)
+    return 1.5 * fine, 1.5 * coarse
+
+
 def level_paths(level, paths, sde, *, rv_mode, precision, nested, kahan, seed,
                 stream=0, pset=0, diag=False, mlp_params=None, scheme=SCHEME_EM):
     """Per-path payoffs and terms of one MLMC level for the given path indices.
@@ -173,6 +193,9 @@ def level_paths(level, paths, sde, *, rv_mode, precision, nested, kahan, seed,
         Pf = fp.to64(payoff(Xf, kind, cp[4]))
         Pc = fp.to64(payoff(Xc, kind, cp[4])) if level >= 1 else np.zeros(paths.size)
         out["Pf_bar"], out["Pc_bar"] = Pf, Pc
+        if rv_mode == RV_MLP and scheme == SCHEME_EM:
+            out["Pf_bar_allow"], out["Pc_bar_allow"] = _mlp_payoff_allowance(
+                level, Zt, _mlp.approx_icdf_allowance(w, mlp_params), cp, fp.to64(Xf), fp.to64(Xc))
         out["Xf_bar"] = fp.to64(Xf)
         two_bar = Pf - Pc
         terms[TERM_TWO_WAY] = two_bar

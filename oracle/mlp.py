@@ -26,8 +26,12 @@ instruction that forms its argument:
 formed in binary32 (sums in index order) and rounded once to binary16.  Inference: the input
 2u' is the word's 2 xm + 1 rounded to binary32 times 2^-32, r = sqrt(-2 ln 2u'), x = r C - 1
 with C = R_32(1 / R_SCALE), rounded to binary16; the first layer is one binary16 fused
-multiply-add per unit (a single rounding); the 16 x 16 layer takes binary16 activations and
-accumulates in binary32 (here: exactly); the output layer is binary32 (here: exact).
+multiply-add per unit (a single rounding); the 16 x 16 layer takes binary16 activations,
+accumulates in binary32 (here: exactly) and its result is rounded to binary16 before the
+clamp, c2 = clamp01(R_16(A2 c1 + a2)); the output layer takes those binary16 activations and
+accumulates in binary32 (here: exactly).  Where A2 c1 + a2 lies so close to a rounding
+boundary of binary16 that the binary32 accumulation may land on either side, both roundings
+are correct; ``c2_allowance`` bounds what that can change in y.
 
 Z~ is bounded for the law of 32-bit words (r <= 6.7, |y| <= |a3| + sum |A3|), so Assumption
 2.1's boundedness holds.  Parameters are one flat vector of 321 values in the order W1(16),
@@ -206,14 +210,42 @@ def input16(r):
     return (r * C_INPUT - 1.0).astype(np.float16).astype(np.float64)
 
 
+def _r16(v):
+    """Round to binary16 (nearest, ties to even; NumPy converts float64 directly)."""
+    return np.asarray(v, dtype=np.float64).astype(np.float16).astype(np.float64)
+
+
+def _layers(q, x16):
+    A1, a1, A2, a2, A3, a3 = unpack(q)
+    c1 = np.clip(_r16(np.outer(x16, A1) + a1), 0.0, 1.0)  # one rounding of the exact A1 x + a1
+    d = c1 @ A2.T + a2                                     # exact up to float64 rounding
+    return c1, d, A2, a2, A3, a3
+
+
 def eval_deployed(q, x16):
     """y of the deployed model q at binary16 inputs x16: the first layer's fused binary16
-    multiply-add (exact in float64, rounded once), the other layers exact."""
-    A1, a1, A2, a2, A3, a3 = unpack(q)
-    z1 = (np.outer(x16, A1) + a1).astype(np.float16).astype(np.float64)
-    c1 = np.clip(z1, 0.0, 1.0)
-    c2 = np.clip(c1 @ A2.T + a2, 0.0, 1.0)
-    return c2 @ A3 + a3
+    multiply-add (exact in float64, rounded once), the second layer's sum exact and rounded
+    once to binary16, the output layer exact."""
+    c1, d, A2, a2, A3, a3 = _layers(q, np.asarray(x16, dtype=np.float64))
+    return np.clip(_r16(d), 0.0, 1.0) @ A3 + a3
+
+
+# binary32 accumulation of the 16 products and the bias of a second-layer unit, in any order:
+# |computed - exact| <= 16 u (|a2| + sum |A2 c1|), u = 2^-24 (each of at most 16 additions
+# rounds once, relative to a partial sum bounded by that total)
+C2_REL = 16 * 2.0 ** -24
+
+
+def c2_allowance(q, x16, rel=C2_REL):
+    """Per sample, the most y can change when the binary16 rounding of a second-layer sum
+    d = A2 c1 + a2 is taken from a binary32 value within delta = rel (|a2| + sum |A2 c1|) of
+    d: units whose interval [d - delta, d + delta] straddles a rounding boundary of binary16
+    (inside the clamp's range) may yield any clamped rounding between the two ends."""
+    c1, d, A2, a2, A3, a3 = _layers(q, np.asarray(x16, dtype=np.float64))
+    delta = rel * (np.abs(c1) @ np.abs(A2).T + np.abs(a2))
+    lo = np.clip(_r16(d - delta), 0.0, 1.0)
+    hi = np.clip(_r16(d + delta), 0.0, 1.0)
+    return (hi - lo) @ np.abs(A3)
 
 
 def approx_icdf(x_words, q, precision, x16=None):
@@ -226,6 +258,15 @@ def approx_icdf(x_words, q, precision, x16=None):
     z = eval_deployed(q, xi) - r
     z = np.where(s, -z, z).reshape(shape)
     return fp.rn(precision, z)
+
+
+def approx_icdf_allowance(x_words, q, x16=None, rel=C2_REL):
+    """``c2_allowance`` of each word's variable (|Z~| changes as |y| does)."""
+    shape = np.shape(x_words)
+    _, xm = mirror(np.ravel(x_words))
+    r, _ = radius(xm)
+    xi = input16(r) if x16 is None else np.ravel(x16)
+    return c2_allowance(q, xi, rel).reshape(shape)
 
 
 def input16_neighbours(x_words, delta):

@@ -422,7 +422,7 @@ __device__ __forceinline__ void run_row(const LevelParams& prm, uint64_t row, ui
 // SHORT: the instance for levels with fewer than 4 fine steps (exact variables one word at a time).
 // SCHEME: MLMC_SCHEME_EM or MLMC_SCHEME_MILSTEIN.
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RV == MLMC_RV_MLP || SHORT ? 1 : (PREC == MLMC_FP32 || PREC == MLMC_FP64) ? 7 : PREC == MLMC_FP16 ? 6 : 1))) void level_kernel(const LevelParams prm) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHORT ? 1 : RV == MLMC_RV_MLP ? 6 : (PREC == MLMC_FP32 || PREC == MLMC_FP64) ? 7 : PREC == MLMC_FP16 ? 6 : 1))) void level_kernel(const LevelParams prm) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kDyadic = (RV == MLMC_RV_PWL16 || RV == MLMC_RV_CUBIC16);
     constexpr bool kPconst = (RV == MLMC_RV_PCONST4096);
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RV == MLMC_
     __shared__ AT s_tab[(kDyadic || kPconst) && !kTab16 ? kTabN : 1];
     __shared__ __half s_tab16[kTab16 ? kTabN : 1];
     __shared__ double s_tab64[(kDyadic || kPconst) && DIAG ? kTabN : 1];
-    __shared__ float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];
+    __shared__ __align__(16) float s_mlp[RV == MLMC_RV_MLP ? kMlpImage : 1];  // 16-byte operand loads
     // the exact variable's top cells
     constexpr size_t kExBytes = (RV == MLMC_RV_EXACT || NESTED) ? sizeof(ExactCols) : 0;
     __shared__ __align__(16) unsigned char s_ex_raw[kExBytes ? kExBytes : 16];

@@ -6,8 +6,9 @@
 // activation is the clamp to [0, 1] of the instruction that forms its argument):
 //   2u = R_32(2 xm + 1) 2^-32, r = sqrt(-2 ln 2u), x = R_16(r C - 1), C = R_32(1 / 3.4),
 //   c1 = clamp01(A1 x + a1)            (packed binary16 fused multiply-add, clamped),
-//   c2 = clamp01(A2 c1 + a2)           (binary16 matrix instruction, binary32 accumulation),
-//   y  = A3 . c2 + a3                  (binary32),
+//   c2 = clamp01(R_16(A2 c1 + a2))     (binary16 matrix instruction, binary32 accumulation,
+//                                       rounded to binary16 and clamped in one conversion),
+//   y  = A3 . c2 + a3                  (binary16 matrix instruction, binary32 accumulation),
 //   Z~ = y - r (u < 1/2), r - y (u >= 1/2);
 // y learns the smooth residual Phi^{-1}(u') + r.  The parameters are binary16 values staged
 // in LDS widened to binary32; r uses the hardware base-2 logarithm and square root (no
@@ -23,10 +24,19 @@ namespace mlmc {
 
 constexpr int kMlpHidden = 16;
 constexpr int kMlpParams = 16 + 16 + 256 + 16 + 16 + 1;  // 321
-constexpr int kMlpImage = 336;                           // padded image length
 constexpr float kMlpRScale = 3.4f;
 // offsets of the parameter blocks in the flat vector
 constexpr int kW1 = 0, kB1 = 16, kW2 = 32, kB2 = 288, kW3 = 304, kB3 = 320;
+// The inference image (binary32 words): the deployed parameters widened to binary32 at the
+// offsets above (padded to 336), then the matrix-instruction operands of mlp_eval_wave already
+// packed as binary16 pairs, so that a wavefront loads them without conversions:
+//   kPkL1   16 words: row g: (A1[4g], A1[4g+1]), (A1[4g+2], A1[4g+3]), (a1[4g], a1[4g+1]),
+//                     (a1[4g+2], a1[4g+3])
+//   kPkA2  128 words: lane 16 g + c: (A2[c][4g], A2[c][4g+1]), (A2[c][4g+2], A2[c][4g+3])
+//   kPkA3  128 words: block b, r = c / 4, row g: A3[4g .. 4g+3] as two pairs when r = b, else 0
+//   kPkB3    4 words: a3 four times (binary32)
+constexpr int kPkL1 = 336, kPkA2 = 352, kPkA3 = 480, kPkB3 = 608;
+constexpr int kMlpImage = 612;
 
 // r = sqrt(-2 ln(2u')) in binary64 for the mirrored word xm, u' = (xm + 1/2) 2^-32 (the
 // input of the training pairs).
@@ -61,40 +71,38 @@ __device__ __forceinline__ mlp_h2 mlp_pair(float lo, float hi) {
 // 16 (n / 4) + s, element n % 4.  For block b (the samples of lanes 16 b + c), lane 16 g + c
 // evaluates the first-layer units 4 g .. 4 g + 3 of sample 16 b + c (two packed fused
 // multiply-adds on that sample's input): the B operand.  A = A2, C = a2, so D holds the
-// second layer's arguments; each lane clamps its four units, weighs them with A3, and the
-// partial sums are added over the four lane groups (two lane-permutation swaps, no LDS), lane
-// 16 g + c keeping block g: its own sample.
+// second layer's arguments in exactly the B layout of the next product: one conversion to
+// binary16 with the clamp modifier per pair of units gives c2 as a B operand.  The output
+// layer is a second product whose A operand is A3 in the rows n of block b (n / 4 = b) and
+// zero elsewhere, accumulated over the four blocks from C = a3: row n of the result then holds
+// y of sample 16 (n / 4) + s, so lane 16 g + c finds its own sample's y in every element.
 __device__ __forceinline__ float mlp_eval_wave(uint32_t x16x2, const float* __restrict__ W) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t c = lane & 15u, g = lane >> 4;
-    const uint32_t k0 = 4u * g;
-    const mlp_h2 w1a = mlp_pair(W[kW1 + k0], W[kW1 + k0 + 1]), w1b = mlp_pair(W[kW1 + k0 + 2], W[kW1 + k0 + 3]);
-    const mlp_h2 b1a = mlp_pair(W[kB1 + k0], W[kB1 + k0 + 1]), b1b = mlp_pair(W[kB1 + k0 + 2], W[kB1 + k0 + 3]);
-    const mlp_h4 w2 = {(_Float16)W[kW2 + c * kMlpHidden + k0], (_Float16)W[kW2 + c * kMlpHidden + k0 + 1],
-                       (_Float16)W[kW2 + c * kMlpHidden + k0 + 2], (_Float16)W[kW2 + c * kMlpHidden + k0 + 3]};
-    const mlp_f4 b2 = {W[kB2 + k0], W[kB2 + k0 + 1], W[kB2 + k0 + 2], W[kB2 + k0 + 3]};
-    float part[4];
+    const float4 l1 = *(const float4*)(W + kPkL1 + 4 * g);
+    const mlp_h2 w1a = __builtin_bit_cast(mlp_h2, l1.x), w1b = __builtin_bit_cast(mlp_h2, l1.y);
+    const mlp_h2 b1a = __builtin_bit_cast(mlp_h2, l1.z), b1b = __builtin_bit_cast(mlp_h2, l1.w);
+    const mlp_h4 w2 = __builtin_bit_cast(mlp_h4, *(const float2*)(W + kPkA2 + 2 * lane));
+    const mlp_f4 b2 = __builtin_bit_cast(mlp_f4, *(const float4*)(W + kB2 + 4 * g));
+    const float* a3 = W + kPkA3 + 2 * (4 * (c >> 2) + g);
+    mlp_f4 y = __builtin_bit_cast(mlp_f4, *(const float4*)(W + kPkB3));
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const mlp_h2 xb = __builtin_bit_cast(mlp_h2, (uint32_t)__shfl((int)x16x2, 16 * b + (int)c, kWave));
         const mlp_h2 h01 = mlp_unit_pair(w1a, xb, b1a), h23 = mlp_unit_pair(w1b, xb, b1b);
         const mlp_h4 bop = {h01[0], h01[1], h23[0], h23[1]};
         const mlp_f4 d = __builtin_amdgcn_mfma_f32_16x16x16f16(w2, bop, b2, 0, 0, 0);
-        float p = 0.0f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            p = __builtin_fmaf(W[kW3 + k0 + r], __builtin_amdgcn_fmed3f(d[r], 0.0f, 1.0f), p);
-        part[b] = p;
+        // round to binary16, then clamp (the same as clamping first: 0 and 1 are binary16
+        // values and rounding is monotone); one conversion with the clamp modifier per pair
+        const mlp_h2 zero = {(_Float16)0.0f, (_Float16)0.0f}, one = {(_Float16)1.0f, (_Float16)1.0f};
+        mlp_h2 c01 = {(_Float16)d[0], (_Float16)d[1]}, c23 = {(_Float16)d[2], (_Float16)d[3]};
+        c01 = __builtin_elementwise_min(__builtin_elementwise_max(c01, zero), one);
+        c23 = __builtin_elementwise_min(__builtin_elementwise_max(c23, zero), one);
+        const mlp_h4 c2 = {c01[0], c01[1], c23[0], c23[1]};
+        const mlp_h4 w3 = __builtin_bit_cast(mlp_h4, *(const float2*)(a3 + 32 * b));
+        y = __builtin_amdgcn_mfma_f32_16x16x16f16(w3, c2, y, 0, 0, 0);
     }
-    // sum over the four lane groups, each lane keeping its own block: swapping the lane halves
-    // pairs block 0 with 2 and 1 with 3 (lanes 0..31 keep blocks 0, 1), swapping odd and even
-    // rows of 16 lanes leaves row g with block g
-    const auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[0]), __float_as_uint(part[2]), false, false);
-    const auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(part[1]), __float_as_uint(part[3]), false, false);
-    const float q0 = __uint_as_float(s02[0]) + __uint_as_float(s02[1]);
-    const float q1 = __uint_as_float(s13[0]) + __uint_as_float(s13[1]);
-    const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(q0), __float_as_uint(q1), false, false);
-    return (__uint_as_float(t[0]) + __uint_as_float(t[1])) + W[kB3];
+    return y[0];
 }
 
 // The learned approximate variable of every lane's word (all 64 lanes together).

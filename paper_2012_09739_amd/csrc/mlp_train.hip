@@ -175,30 +175,57 @@ __global__ void fill_kernel(float* __restrict__ p, uint32_t n, float v, uint32_t
 // Inference image: the deployed form of the parameters (c = (h + 1) / 2 for every hard-tanh
 // unit h), A1 = W1 / 2, a1 = (b1 + 1) / 2, A2 = W2, a2 = (b2 - W2 1 + 1) / 2, A3 = 2 W3,
 // a3 = b3 - W3 . 1, each formed in binary32 (sums in index order), rounded once to binary16
-// and stored widened to binary32.
+// and stored widened to binary32, followed by the same binary16 values packed as the matrix
+// operands of the inference (layout in mlp.h).
+__device__ __forceinline__ float pack_halves(_Float16 lo, _Float16 hi) {
+    return __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, lo) |
+                           ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16));
+}
+
 __global__ void deploy_kernel(const float* __restrict__ params, float* __restrict__ image) {
+    __shared__ _Float16 h[kMlpParams];
     const int i = threadIdx.x;
-    if (i >= kMlpImage) return;
-    float v = 0.0f;
-    if (i < kB1) {
-        v = params[i] * 0.5f;
-    } else if (i < kW2) {
-        v = (params[i] + 1.0f) * 0.5f;
-    } else if (i < kB2) {
-        v = params[i];
-    } else if (i < kW3) {
-        const int n = i - kB2;
-        float s = 0.0f;
-        for (int k = 0; k < kMlpHidden; ++k) s = __fadd_rn(s, params[kW2 + n * kMlpHidden + k]);
-        v = __fmul_rn(__fadd_rn(__fadd_rn(params[i], -s), 1.0f), 0.5f);
-    } else if (i < kB3) {
-        v = params[i] * 2.0f;
-    } else if (i == kB3) {
-        float s = 0.0f;
-        for (int k = 0; k < kMlpHidden; ++k) s = __fadd_rn(s, params[kW3 + k]);
-        v = __fadd_rn(params[i], -s);
+    if (i < kMlpParams) {
+        float v = 0.0f;
+        if (i < kB1) {
+            v = params[i] * 0.5f;
+        } else if (i < kW2) {
+            v = (params[i] + 1.0f) * 0.5f;
+        } else if (i < kB2) {
+            v = params[i];
+        } else if (i < kW3) {
+            const int n = i - kB2;
+            float s = 0.0f;
+            for (int k = 0; k < kMlpHidden; ++k) s = __fadd_rn(s, params[kW2 + n * kMlpHidden + k]);
+            v = __fmul_rn(__fadd_rn(__fadd_rn(params[i], -s), 1.0f), 0.5f);
+        } else if (i < kB3) {
+            v = params[i] * 2.0f;
+        } else {
+            float s = 0.0f;
+            for (int k = 0; k < kMlpHidden; ++k) s = __fadd_rn(s, params[kW3 + k]);
+            v = __fadd_rn(params[i], -s);
+        }
+        h[i] = (_Float16)__float2half_rn(v);
+        image[i] = (float)h[i];
+    } else if (i < kPkL1) {
+        image[i] = 0.0f;
     }
-    image[i] = i < kMlpParams ? __half2float(__float2half_rn(v)) : 0.0f;
+    __syncthreads();
+    if (i < kPkA2 - kPkL1) {                       // first layer, per row g
+        const int g = i / 4, q = i % 4;
+        const int base = (q < 2 ? kW1 : kB1) + 4 * g + 2 * (q & 1);
+        image[kPkL1 + i] = pack_halves(h[base], h[base + 1]);
+    } else if (i < kPkA3 - kPkL1) {                // 16 x 16 layer, per lane
+        const int j = i - (kPkA2 - kPkL1), lane = j / 2, c = lane % 16, g = lane / 16;
+        const int base = kW2 + c * kMlpHidden + 4 * g + 2 * (j & 1);
+        image[kPkL1 + i] = pack_halves(h[base], h[base + 1]);
+    } else if (i < kPkB3 - kPkL1) {                // output layer, masked per block
+        const int j = i - (kPkA3 - kPkL1), e = j / 2, b = e / 16, r = (e / 4) % 4, g = e % 4;
+        const int base = kW3 + 4 * g + 2 * (j & 1);
+        image[kPkL1 + i] = r == b ? pack_halves(h[base], h[base + 1]) : 0.0f;
+    } else if (i < kMlpImage - kPkL1) {
+        image[kPkL1 + i] = (float)h[kB3];
+    }
 }
 
 int ck(hipError_t e, const char* what) {
@@ -215,6 +242,7 @@ struct DevBuf {
 }  // namespace
 
 hipError_t launch_mlp_deploy(const float* d_params, float* image, hipStream_t s) {
+    static_assert(kMlpImage - kPkL1 <= 384 && kMlpParams <= 384 && kPkL1 <= 384, "one thread per entry");
     hipLaunchKernelGGL(deploy_kernel, dim3(1), dim3(384), 0, s, d_params, image);
     return hipGetLastError();
 }

@@ -139,7 +139,30 @@ VR_CHAIN32(VALU_MUL_F16, uint32_t, VR_32_2("v_mul_f16"))
 VR_CHAIN32(VALU_PK_ADD_F16, uint32_t, VR_32_2("v_pk_add_f16"))
 VR_CHAIN32(VALU_CVT_PK_F16_F32, uint32_t, asm volatile("v_cvt_pk_f16_f32 %0, %1, %2" : "+v"(r) : "v"(a), "v"(b)))
 VR_CHAIN32(VALU_CVT_F32_U32, uint32_t, asm volatile("v_cvt_f32_u32 %0, %1" : "+v"(r) : "v"(a)))
+VR_CHAIN32(VALU_MAX_F32_CLAMP, float, asm volatile("v_max_f32_e64 %0, %0, %1 clamp" : "+v"(r) : "v"(a)))
+VR_CHAIN32(VALU_SUB_U32_CLAMP, uint32_t, asm volatile("v_sub_u32_e64 %0, %0, %1 clamp" : "+v"(r) : "v"(a)))
+VR_CHAIN32(VALU_LSHR_B32, uint32_t, VR_32_2("v_lshrrev_b32"))
+VR_CHAIN32(VALU_FMA_MIX_F16, float, VR_32_3("v_fma_mixlo_f16"))
+VR_CHAIN32(VALU_BITOP3_B16, uint32_t,
+           asm volatile("v_bitop3_b16 %0, %1, %2, %0 bitop3:0x96" : "+v"(r) : "v"(a), "v"(b)))
 #undef VR_CHAIN32
+template <>
+struct Chain<VALU_CMP_U32> {
+    uint32_t r;
+    uint64_t m;  // each chain's own scalar register pair
+    __device__ void step(uint32_t a, uint32_t) { asm volatile("v_cmp_gt_u32_e64 %0, %1, %2" : "=s"(m) : "v"(a), "v"(r)); }
+};
+template <>
+struct Chain<VALU_LOG_F32> {
+    float r;
+    // from the loop-invariant operand: a chain of logarithms would leave the finite range
+    __device__ void step(float a, float) { asm volatile("v_log_f32 %0, %1" : "+v"(r) : "v"(a)); }
+};
+template <>
+struct Chain<VALU_SQRT_F32> {
+    float r;
+    __device__ void step(float, float) { VR_32_1("v_sqrt_f32"); }
+};
 template <>
 struct Chain<VALU_CVT_F64_U32> {
     double r;
@@ -208,6 +231,9 @@ __device__ void seed(Chain<OP>& c, uint32_t lane, int k) {
     if constexpr (OP == VALU_MAD_U64_U32) {
         c.r = (uint64_t)lane * 2654435761u + k;
         c.carry = 0;
+    } else if constexpr (OP == VALU_CMP_U32) {
+        c.r = lane * 747796405u + (uint32_t)k;
+        c.m = 0;
     }
     else if constexpr (OP == VALU_CVT_F64_F32) {
         c.r = 1.0;
@@ -310,7 +336,9 @@ extern "C" int valu_rate(int op, int waves_per_simd, uint32_t iters, double* lan
             VR_CASE(VALU_LSHL_OR_B32) VR_CASE(VALU_CNDMASK_B32) VR_CASE(VALU_PERM_B32) VR_CASE(VALU_AND_B32)
             VR_CASE(VALU_ASHR_I32) VR_CASE(VALU_ADD_F16) VR_CASE(VALU_MUL_F16) VR_CASE(VALU_PK_ADD_F16)
             VR_CASE(VALU_CVT_PK_F16_F32) VR_CASE(VALU_CVT_F32_U32) VR_CASE(VALU_CVT_F64_U32) VR_CASE(VALU_LSHL_B64)
-            VR_CASE(VALU_LSHL_ADD_U64) VR_CASE(VALU_MOV_B64)
+            VR_CASE(VALU_LSHL_ADD_U64) VR_CASE(VALU_MOV_B64) VR_CASE(VALU_MAX_F32_CLAMP)
+            VR_CASE(VALU_SUB_U32_CLAMP) VR_CASE(VALU_LSHR_B32) VR_CASE(VALU_FMA_MIX_F16) VR_CASE(VALU_BITOP3_B16)
+            VR_CASE(VALU_LOG_F32) VR_CASE(VALU_SQRT_F32) VR_CASE(VALU_CMP_U32)
 #undef VR_CASE
             default: e = hipErrorInvalidValue;
         }

@@ -82,9 +82,13 @@ FEATURE_DELTA = 1e-6
 
 
 def test_inference_matches_oracle_on_seeded_weights():
-    """The learned variable against the oracle's deployed model.  Where the network input
-    r C - 1 lies within FEATURE_DELTA of a binary16 rounding boundary, either rounding of it
-    is a correct binary16 input; the variable must then match the oracle for one of the two."""
+    """The learned variable against the oracle's deployed model.  Two roundings are taken
+    from values the hardware may form in either of two correct ways: where the network input
+    r C - 1 lies within FEATURE_DELTA of a binary16 rounding boundary, either rounding of it is
+    a correct binary16 input, and where a second-layer sum lies that close to one (within the
+    bound of any binary32 accumulation order), either rounding of it is; the variable must
+    match the oracle for one of the two inputs, within the tolerance plus the oracle's bound
+    on what the second-layer roundings can change."""
     torch = torch_cuda()
     p = W.mlp_initial_params(5) + np.random.default_rng(6).normal(0, 0.1, mlp.N_PARAMS)
     M.mlmc_mlp_load(dev(p))
@@ -95,16 +99,25 @@ def test_inference_matches_oracle_on_seeded_weights():
     lo, hi = mlp.input16_neighbours(words, FEATURE_DELTA)
     assert np.mean(lo != hi) < 0.01
     want = [mlp.approx_icdf(words, q, fp.FP64, x16=x16) for x16 in (lo, hi)]
+    allow = [mlp.approx_icdf_allowance(words, q, x16=x16) for x16 in (lo, hi)]
+    # the second-layer rounding is decided exactly for most words
+    assert np.mean(allow[0] > 0) < 0.75 and np.max(allow[0]) < 2e-3
     for prec in (M.MLMC_FP64, M.MLMC_FP32, M.MLMC_FP16):
         got = gpu_icdf(words, M.MLMC_RV_MLP, prec)
         tol = 1e-5 if prec != M.MLMC_FP16 else 4e-3
-        ok = (np.abs(got - want[0]) <= tol) | (np.abs(got - want[1]) <= tol)
+        ok = (np.abs(got - want[0]) <= tol + allow[0]) | (np.abs(got - want[1]) <= tol + allow[1])
         assert np.all(ok), (prec, words[~ok][:5], got[~ok][:5], want[0][~ok][:5])
+        if prec == M.MLMC_FP32:
+            exact = (allow[0] == 0) & (lo == hi)
+            assert np.all(np.abs(got[exact] - want[0][exact]) <= tol)
     zm = gpu_icdf(np.uint64(2 ** 32 - 1) - words, M.MLMC_RV_MLP, M.MLMC_FP32)
     np.testing.assert_array_equal(zm, -gpu_icdf(words, M.MLMC_RV_MLP, M.MLMC_FP32))
 
 
 def test_nested_mlp_paths_match_oracle():
+    """Per-path payoffs of the nested estimator with the learned variable: the exact pair to
+    1e-13, the approximate pair to the binary32 bar plus the oracle's first-order bound on
+    what the two correct roundings of each variable's second-layer sums can change."""
     torch = torch_cuda()
     p = W.mlp_initial_params(5) + np.random.default_rng(6).normal(0, 0.1, mlp.N_PARAMS)
     M.mlmc_mlp_load(dev(p))
@@ -114,8 +127,12 @@ def test_nested_mlp_paths_match_oracle():
     o = mlmc.level_paths(level, np.arange(n), W.GBM_CALL, rv_mode=mlmc.RV_MLP, precision=fp.FP32, nested=True,
                          kahan=True, seed=8, stream=1, mlp_params=q)
     assert np.max(np.abs(g["pf_hat"] - o["Pf_hat"])) <= 1e-13
-    assert np.all(close(g["pf_bar"], o["Pf_bar"], 1e-5))
-    assert np.all(close(g["pc_bar"], o["Pc_bar"], 1e-5))
+    for key, ref in (("pf_bar", "Pf_bar"), ("pc_bar", "Pc_bar")):
+        err = np.abs(g[key] - o[ref])
+        assert np.all(err <= 1e-5 * np.maximum(np.abs(o[ref]), 1.0) + o[ref + "_allow"]), key
+    # paths whose variables all round their second layer exactly meet the plain bar
+    exact = (o["Pf_bar_allow"] == 0) & (o["Pc_bar_allow"] == 0)
+    assert np.all(close(g["pf_bar"][exact], o["Pf_bar"][exact], 1e-5))
 
 
 @pytest.fixture(scope="module")
