@@ -214,7 +214,10 @@ int mlmc_paths(const mlmc_level_args_t* args, double* d_pf_hat, double* d_pc_hat
 
 /* The uniform words the level kernels consume (parity checks): d_words (device,
  * n_paths * n_steps uint32, row-major [path][step]) for paths path0.. of the given
- * seed, Philox stream, level and pset.  n_steps <= 2^24. */
+ * seed, Philox stream, level and pset.  n_steps <= 2^24, and at most 2^level at levels 0
+ * and 1, where one Philox call serves 4 / 2^level consecutive paths (counter (0, path div
+ * G, (stream << 16) | level, pset), word (path mod G) 2^level + n); from level 2 on the
+ * counter is (n >> 2, path, (stream << 16) | level, pset) and step n takes word n & 3. */
 int mlmc_uniforms(uint64_t seed, uint32_t stream, int level, uint32_t pset, uint64_t path0,
                   uint64_t n_paths, uint32_t n_steps, uint32_t* d_words, void* hip_stream);
 

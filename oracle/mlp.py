@@ -148,8 +148,10 @@ def training_words(seed, first, n):
     31), which spreads the samples over the 31 dyadic scales of (0, 1/2)."""
     from . import philox
     i = np.arange(first, first + n, dtype=np.uint64)
-    w = philox.words(seed, 2, 0, 0, i, 2)
-    w0, w1 = w[:, 0].astype(np.uint64), w[:, 1].astype(np.uint64)
+    seed = int(seed)
+    r = philox.philox4x32_10(np.uint64(0), i, np.uint64(2 << 16), np.uint64(0), np.uint64(seed & 0xFFFFFFFF),
+                             np.uint64((seed >> 32) & 0xFFFFFFFF))
+    w0, w1 = r[0], r[1]
     xm_u = np.where(w0 >= np.uint64(2 ** 31), np.uint64(2 ** 32 - 1) - w0, w0)
     xm_t = (w0 >> np.uint64(1)) >> (w1 % np.uint64(31))
     return np.where(i % np.uint64(2) == 0, xm_u, xm_t)

@@ -10,9 +10,12 @@ bumped by two Weyl constants between rounds.
 
 Counter layout (the build's reading, fixed for every implementation):
     key     = (seed mod 2^32, seed >> 32)
-    counter = (n >> 2, path, (stream << 16) | level, pset)
-and fine step n of a path uses output word (n & 3) of that call.  The mapping depends
-only on (seed, stream, level, pset, path, n) -- never on how work is scheduled.
+    levels >= 2:  counter = (n >> 2, path, (stream << 16) | level, pset), word n & 3
+    levels 0, 1:  a path has S = 2^level < 4 steps, and one call serves G = 4 / S
+                  consecutive paths: counter = (0, path div G, (stream << 16) | level, pset),
+                  word (path mod G) S + n
+so that no output word is drawn and left unused.  The mapping depends only on (seed,
+stream, level, pset, path, n) -- never on how work is scheduled.
 
 Pinned by ``tests/test_oracle_philox.py`` against rocRAND's Philox4x32-10 engine (a
 library implementation of the same published generator) compiled for the host.
@@ -52,7 +55,7 @@ def words(seed, stream, level, pset, paths, n_steps):
     """All uniform words of ``n_steps`` fine steps for each path in ``paths``.
 
     Returns a uint32 array of shape (len(paths), n_steps); entry [i, n] is the word that
-    fine step n of path ``paths[i]`` consumes.
+    fine step n of path ``paths[i]`` consumes.  At levels 0 and 1 n_steps is at most 2^level.
     """
     paths = np.asarray(paths, dtype=np.uint64)
     seed = int(seed)
@@ -60,6 +63,18 @@ def words(seed, stream, level, pset, paths, n_steps):
     k1 = np.uint64((seed >> 32) & 0xFFFFFFFF)
     c2 = np.uint64(((int(stream) & 0xFFFF) << 16) | (int(level) & 0xFFFF))
     c3 = np.uint64(int(pset) & 0xFFFFFFFF)
+    if int(level) < 2:
+        S = 1 << int(level)
+        G = 4 // S
+        if int(n_steps) > S:
+            raise ValueError("levels 0 and 1 have at most 2^level steps")
+        r = philox4x32_10(np.uint64(0), paths // np.uint64(G), c2, c3, k0, k1)
+        r = np.stack(r, axis=1).astype(np.uint32)                  # (paths, 4)
+        first = (paths % np.uint64(G)).astype(np.int64) * S        # word of step 0
+        out = np.empty((paths.size, int(n_steps)), dtype=np.uint32)
+        for n in range(int(n_steps)):
+            out[:, n] = r[np.arange(paths.size), first + n]
+        return out
     n_calls = (int(n_steps) + 3) // 4
     out = np.empty((paths.size, 4 * n_calls), dtype=np.uint32)
     for q in range(n_calls):
@@ -71,6 +86,14 @@ def words(seed, stream, level, pset, paths, n_steps):
 
 def word(seed, stream, level, pset, path, n):
     """The single word that fine step ``n`` of ``path`` consumes (scalar helper)."""
+    if level < 2:
+        S = 1 << level
+        G = 4 // S
+        r = philox4x32_10(np.uint64(0), np.uint64(path // G),
+                          np.uint64(((stream & 0xFFFF) << 16) | (level & 0xFFFF)),
+                          np.uint64(pset), np.uint64(seed & 0xFFFFFFFF),
+                          np.uint64((seed >> 32) & 0xFFFFFFFF))
+        return int(r[(path % G) * S + n])
     r = philox4x32_10(np.uint64(n >> 2), np.uint64(path),
                       np.uint64(((stream & 0xFFFF) << 16) | (level & 0xFFFF)),
                       np.uint64(pset), np.uint64(seed & 0xFFFFFFFF),

@@ -774,6 +774,8 @@ int mlmc_uniforms(uint64_t seed, uint32_t stream, int level, uint32_t pset, uint
     if (stream > 0xFFFFu) return fail(MLMC_EINVAL, "stream %u exceeds 65535", stream);
     if (level < 0 || level > 0xFFFF) return fail(MLMC_EINVAL, "level %d outside 0..65535", level);
     if (n_steps > (1u << kMaxLevel)) return fail(MLMC_EINVAL, "n_steps exceeds 2^%d", kMaxLevel);
+    if (level < 2 && n_steps > (1u << level))
+        return fail(MLMC_EINVAL, "level %d has at most %u steps (its calls are shared by paths)", level, 1u << level);
     if (path0 + n_paths > (1ull << 32)) return fail(MLMC_EINVAL, "path0 + n_paths exceeds 2^32");
     DevState* st;
     int rc = device_state(&st);

@@ -71,7 +71,7 @@ hipError_t launch_reduce(const double* partials, uint64_t n_rows, double* stage,
 // reduces the row once.  At the coarse levels a chunk is only a few steps long, so the wave
 // reduction and the per-wave set-up would otherwise cost more than the paths; grouping depends
 // on the level alone, so every call and batch item of a level reduces its paths alike.
-__host__ __device__ inline uint32_t row_chunks(int level) { return level >= 2 ? 1u : (8u >> level); }
+__host__ __device__ constexpr inline uint32_t row_chunks(int level) { return level >= 2 ? 1u : (8u >> level); }
 __host__ __device__ inline uint64_t rows_of(uint64_t n_chunks, int level) {
     const uint64_t g = row_chunks(level);
     return (n_chunks + g - 1) / g;

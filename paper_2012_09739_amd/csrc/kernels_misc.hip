@@ -29,6 +29,19 @@ __global__ __launch_bounds__(kReduceBlock) void reduce_chunks_stage2(const doubl
 
 __global__ void uniforms_kernel(uint32_t k0, uint32_t k1, uint32_t ctr2, uint32_t pset, uint64_t path0,
                                 uint64_t n_paths, uint32_t n_steps, uint32_t* __restrict__ words) {
+    const uint32_t level = ctr2 & 0xFFFFu;
+    if (level < 2) {
+        // one call per G = 4 >> level consecutive paths (n_steps <= 2^level, checked by the host)
+        const uint32_t shift = 2 - level;
+        for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_paths;
+             p += (uint64_t)gridDim.x * blockDim.x) {
+            const uint64_t gp = path0 + p;
+            const Words4 r = philox4x32_10<0>(0u, (uint32_t)(gp >> shift), ctr2, pset, k0, k1);
+            const uint32_t first = ((uint32_t)gp & ((1u << shift) - 1u)) << level;
+            for (uint32_t n = 0; n < n_steps; ++n) words[p * n_steps + n] = r.w[first + n];
+        }
+        return;
+    }
     const uint64_t n_calls = (n_steps + 3) / 4;
     const uint64_t total = n_paths * n_calls;
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;

@@ -188,10 +188,13 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
 // One wave simulates one chunk of 64 paths (128 for binary16: two paths per lane) of one
 // level and adds each lane's (sum, sum of squares) of every term to acc.  s_tab is the
 // coefficient table in the working precision (binary32: prescaled, see prescaled_coeff) and
-// s_tab64 the binary64 one (diagnostic), both in LDS.
+// s_tab64 the binary64 one (diagnostic), both in LDS.  SHORT (levels 0 and 1): the caller
+// draws the words, whose calls several paths share, and names each lane's paths in
+// sh_words / sh_local (chunk is then unused).
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
 __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
-                                            const double* s_tab64, const ExactLds* s_ex, double (&acc)[kPartial]) {
+                                            const double* s_tab64, const ExactLds* s_ex, double (&acc)[kPartial],
+                                            const Words4* sh_words = nullptr, const uint64_t* sh_local = nullptr) {
     constexpr int DEG = (RV == MLMC_RV_CUBIC16) ? 3 : 1;
     constexpr bool kExactOnly = (RV == MLMC_RV_EXACT);
     constexpr bool kNeedExact = kExactOnly || NESTED;
@@ -212,7 +215,7 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
     uint32_t path[L];
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-        local[l] = chunk * kChunk + (uint64_t)l * kWave + lane;
+        local[l] = SHORT ? sh_local[l] : chunk * kChunk + (uint64_t)l * kWave + lane;
         valid[l] = local[l] < prm.n_paths;
         path[l] = (uint32_t)(prm.path_offset + (valid[l] ? local[l] : 0));
     }
@@ -247,7 +250,8 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
     for (uint32_t q = 0; q < n_calls; ++q) {
         Words4 r[L];
 #pragma unroll
-        for (int l = 0; l < L; ++l) r[l] = philox4x32_10(q, path[l], prm.ctr2, prm.pset, prm.key0, prm.key1);
+        for (int l = 0; l < L; ++l)
+            r[l] = SHORT ? sh_words[l] : philox4x32_10(q, path[l], prm.ctr2, prm.pset, prm.key0, prm.key1);
         double zx[L][4];
         if constexpr (kNeedExact) {
             if constexpr (!SHORT) {
@@ -276,9 +280,8 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            // only levels 0 and 1 stop inside a call; the instances with the exact variable
-            // run them as SHORT ones, so their other instance never checks
-            if constexpr (SHORT || !kNeedExact)
+            // only levels 0 and 1 stop inside a call, and they run as SHORT instances
+            if constexpr (SHORT)
                 if (4 * q + i >= prm.n_steps) break;
             const bool coarse = (i & 1) != 0;
             if constexpr (kNeedExact && SHORT) {
@@ -398,6 +401,53 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
 // then one wave reduction into prm.partials[row].  The instances that serve only levels >= 2
 // (every one with the exact variable but the SHORT ones) have one-chunk rows, so their sums
 // need no registers during the steps.
+// Levels 0 and 1 (S = 2^LEVEL fine steps): one Philox call serves the G = 4 / S
+// consecutive paths whose words it holds, so the lanes take a row's paths in groups of G:
+// lane i takes groups k 64 + i of the row (k = 0, 1, ...), draws one call per group (two when
+// the first path index is not a multiple of G), and runs the group's paths L at a time (two
+// packed binary16 paths, else one), each lane adding them in that order.
+template <int LEVEL, int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, int SCHEME>
+__device__ __forceinline__ void short_row_terms(const LevelParams& prm, uint64_t row, uint32_t lane, const void* s_tab_v,
+                                                const double* s_tab64, const ExactLds* s_ex, double (&acc)[kPartial]) {
+    constexpr uint32_t S = 1u << LEVEL, G = 4u >> LEVEL;
+    constexpr uint32_t L = (PREC == MLMC_FP16) ? 2 : 1;
+    constexpr uint32_t kRowPaths = row_chunks(LEVEL) * kWave * L;
+    static_assert(kRowPaths % (kWave * G) == 0 && G % L == 0, "whole groups per lane");
+    const uint64_t first = row * kRowPaths;
+    const uint32_t shift = (uint32_t)(prm.path_offset % G);  // wave-uniform
+    for (uint32_t k = 0; k < kRowPaths / (kWave * G); ++k) {
+        const uint64_t base = first + (uint64_t)G * (k * kWave + lane);  // the group's first path (local)
+        const uint64_t gp = prm.path_offset + base;
+        const Words4 c0 = philox4x32_10(0u, (uint32_t)(gp / G), prm.ctr2, prm.pset, prm.key0, prm.key1);
+        Words4 c1 = c0;
+        if (shift != 0) c1 = philox4x32_10(0u, (uint32_t)(gp / G + 1), prm.ctr2, prm.pset, prm.key0, prm.key1);
+#pragma unroll
+        for (uint32_t j = 0; j < G; j += L) {
+            Words4 w[L] = {};
+            uint64_t loc[L];
+#pragma unroll
+            for (uint32_t l = 0; l < L; ++l) {
+                loc[l] = base + j + l;
+#pragma unroll
+                for (uint32_t n = 0; n < S; ++n) {
+                    // word (shift + j + l) S + n of the two calls, in order
+                    if (shift == 0) {
+                        w[l].w[n] = c0.w[(j + l) * S + n];
+                    } else {
+                        const uint32_t e = (shift + j + l) * S + n;  // uniform, < 8
+                        uint32_t x = c0.w[0];
+#pragma unroll
+                        for (uint32_t t = 1; t < 8; ++t)
+                            if (e == t) x = t < 4 ? c0.w[t] : c1.w[t - 4];
+                        w[l].w[n] = x;
+                    }
+                }
+            }
+            chunk_terms<PREC, RV, NESTED, KAHAN, DIAG, true, SCHEME>(prm, 0, lane, s_tab_v, s_tab64, s_ex, acc, w, loc);
+        }
+    }
+}
+
 template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
 __device__ __forceinline__ void run_row(const LevelParams& prm, uint64_t row, uint32_t lane, const void* s_tab_v,
                                         const double* s_tab64, const ExactLds* s_ex) {
@@ -405,7 +455,10 @@ __device__ __forceinline__ void run_row(const LevelParams& prm, uint64_t row, ui
     double acc[kPartial];
 #pragma unroll
     for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
-    if constexpr (kOneChunkRows) {
+    if constexpr (SHORT) {
+        if (prm.level == 0) short_row_terms<0, PREC, RV, NESTED, KAHAN, DIAG, SCHEME>(prm, row, lane, s_tab_v, s_tab64, s_ex, acc);
+        else short_row_terms<1, PREC, RV, NESTED, KAHAN, DIAG, SCHEME>(prm, row, lane, s_tab_v, s_tab64, s_ex, acc);
+    } else if constexpr (kOneChunkRows) {
         chunk_terms<PREC, RV, NESTED, KAHAN, DIAG, SHORT, SCHEME>(prm, row, lane, s_tab_v, s_tab64, s_ex, acc);
     } else {
         constexpr uint32_t kChunk = kWave * ((PREC == MLMC_FP16) ? 2 : 1);

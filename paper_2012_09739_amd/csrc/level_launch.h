@@ -9,12 +9,9 @@ namespace launch_detail {
 
 template <int PREC, int SCHEME, int RV, bool NESTED, bool KAHAN, bool DIAG>
 hipError_t go(const LevelParams& p, int grid, int block, hipStream_t s) {
-    if constexpr (NESTED || RV == MLMC_RV_EXACT) {
-        if (p.n_steps < 4) {
-            hipLaunchKernelGGL((level_kernel<PREC, RV, NESTED, KAHAN, DIAG, true, SCHEME>), dim3(grid), dim3(block), 0,
-                               s, p);
-            return hipGetLastError();
-        }
+    if (p.n_steps < 4) {  // levels 0 and 1: calls shared by paths
+        hipLaunchKernelGGL((level_kernel<PREC, RV, NESTED, KAHAN, DIAG, true, SCHEME>), dim3(grid), dim3(block), 0, s, p);
+        return hipGetLastError();
     }
     hipLaunchKernelGGL((level_kernel<PREC, RV, NESTED, KAHAN, DIAG, false, SCHEME>), dim3(grid), dim3(block), 0, s, p);
     return hipGetLastError();

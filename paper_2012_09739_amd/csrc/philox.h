@@ -6,10 +6,14 @@
 // ten rounds of two 32x32->64 products with fixed odd multipliers, high halves xor-ed
 // into the other two counter words and the round key, key bumped by Weyl constants.
 //
-// Counter layout used by every kernel of this library:
-//   key = (seed lo32, seed hi32), counter = (n >> 2, path, (stream << 16) | level, pset)
-// and fine step n of a path consumes output word (n & 3).  The words depend only on those
-// six integers, never on the launch shape, so any tuning leaves the samples unchanged.
+// Counter layout used by every kernel of this library: key = (seed lo32, seed hi32) and
+//   levels >= 2: counter = (n >> 2, path, (stream << 16) | level, pset), fine step n of a
+//                path consumes output word (n & 3);
+//   levels 0, 1: the S = 2^level < 4 steps of G = 4 / S consecutive paths share one call,
+//                counter = (0, path / G, (stream << 16) | level, pset), step n of path p
+//                consuming word (p mod G) S + n,
+// so that no word is drawn and left unused.  The words depend only on (seed, stream, level,
+// pset, path, n), never on the launch shape, so any tuning leaves the samples unchanged.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -165,3 +165,11 @@ def test_level_set_validation_before_device():
     assert lib.mlmc_level_set_run(arr, 4097, res, None) == M.MLMC_EINVAL
     assert lib.mlmc_level_set_run(None, 1, res, None) == M.MLMC_EINVAL
     assert lib.mlmc_level_set_run(arr, 1, None, None) == M.MLMC_EINVAL
+
+
+def test_uniforms_reject_more_steps_than_a_coarse_level_has():
+    # levels 0 and 1 share each Philox call between paths: at most 2^level words per path
+    lib = M.lib()
+    for level, n_steps in ((0, 2), (1, 3)):
+        assert lib.mlmc_uniforms(0, 0, level, 0, 0, 0, n_steps, None, None) == M.MLMC_EINVAL
+        assert "steps" in M.mlmc_last_error()

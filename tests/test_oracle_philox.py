@@ -56,6 +56,27 @@ def test_counter_layout_matches_scalar_definition():
             assert int(w[i, n]) == philox.word(seed, stream, level, pset, int(p), n)
 
 
+@pytest.mark.parametrize("level", [0, 1])
+def test_coarse_levels_share_calls_across_paths(level):
+    # levels 0 and 1: one call (0, path div G, ...) for G = 4 / 2^level consecutive paths,
+    # its four words dealt out in path order, every word used once
+    seed, stream, pset = 0xFEDCBA9876543210, 5, 9
+    S, G = 2 ** level, 4 // 2 ** level
+    paths = np.arange(4096, 4096 + 4 * G, dtype=np.uint64)
+    w = philox.words(seed, stream, level, pset, paths, S)
+    for m in range(4):
+        c = philox.philox4x32_10(0, (4096 + m * G) // G, (stream << 16) | level, pset,
+                                 seed & 0xFFFFFFFF, seed >> 32)
+        np.testing.assert_array_equal(w[m * G:(m + 1) * G].ravel(), np.array([int(x) for x in c], dtype=np.uint32))
+        for j in range(G):
+            for n in range(S):
+                assert int(w[m * G + j, n]) == philox.word(seed, stream, level, pset, 4096 + m * G + j, n)
+    # unaligned first path: the same words (they depend on the path, not on the slice)
+    np.testing.assert_array_equal(philox.words(seed, stream, level, pset, paths[1:], S), w[1:])
+    with pytest.raises(ValueError):
+        philox.words(seed, stream, level, pset, paths, S + 1)
+
+
 def test_words_prefix_independent_of_length():
     a = philox.words(0, 0, 5, 0, np.arange(8), 32)
     b = philox.words(0, 0, 5, 0, np.arange(8), 5)
