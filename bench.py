@@ -32,69 +32,73 @@ sys.path.insert(0, ROOT)
 LEVELS = list(range(11))
 N_PATHS = 2 ** 20
 SEED = 0
-# VALU issue peak of MI355X in binary64-equivalent lane-operations ("slots"): 256 CUs x 64
-# lanes x 2.4 GHz (= the binary64 vector peak 78.6 TFLOP/s / 2 flops per FMA).  The weight of
-# an opcode is its issue cost relative to v_fma_f64, from the issue-rate probes
-# (libvalurates.so, bench leg "valu_rates"): 32-bit operations (binary32, integer, logic)
-# issue at twice the binary64 rate and weigh 1/2 (the binary32 vector peak 157.3 TFLOP/s).
+# VALU issue peak of MI355X in slots: a slot is one wavefront instruction at the binary64
+# FMA rate, 64 lane-operations per CU per clock, so the peak is 256 CUs x 64 x 2.4 GHz
+# = 39.32 T lane-slots/s (the binary64 vector peak 78.6 TFLOP/s / 2 flops per FMA).  The
+# issue cost of an opcode in slots is measured by the issue-rate probes (libvalurates.so,
+# report leg "valu_rates"; profiles/valu_issue_rates_gfx950.md): 1/2 for binary32 and
+# scalar binary16 add / mul / fma, 32-bit add / sub / and / xor / shifts, the three-input
+# xor and v_cndmask; 1 for binary64 arithmetic, packed binary16, the 32x32->64 products,
+# conversions, clz, min, lshl_or, perm, med3, compares, clamped v_max_f32 and 64-bit
+# shifts and moves; 2 for scalar binary16 fma, mixed-precision fma, 16-bit bitop3 and the
+# transcendental unit (exp, log, sqrt, rcp).
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 # vector peaks of MI355X (TFLOP/s): binary64 and binary32 published; packed binary16 at the
-# rate the probes measure for v_pk_fma_f16 (two FMAs per lane per instruction)
+# rate the probes measure for v_pk_fma_f16 (one instruction per slot, two FMAs per lane)
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "f16": 157.3}
-# algorithmic binary64-equivalent VALU lane-operations per coupled path-step of the nested
-# binary32 piecewise-linear kernel with Kahan updates, for the minimal operation sequence of
-# this formulation:
-#   Philox4x32-10, a quarter call: 4 products x 2 + 4.5 three-input xors x 1/2     10.25
-#   exact inverse CDF: 13 binary64 operations (x, y = 1 - x^2, t = y - c, the two
-#     binary32 coefficients widened, degree-6 cell polynomial, x G) + 5 32-bit
-#     ones x 1/2 (key, cell index, address, cell centre, deep-cell test)          15.5
-#   binary64 fine and half coarse EM update in the product form of GBM,
-#     X = fma(X, fma(cb, Z, ca), X): fine 2; coarse Z sum + 2 = 3, half of it      3.5
-#   piecewise-linear inverse CDF, binary32: 13 32-bit operations x 1/2             6.5
-#   binary32 fine and half coarse Kahan EM update: (8 + 9/2) x 1/2                 6.25
-ALG_OPS_PER_STEP = 42.0
-# the dominant kernels, each timed alone: HIP events on the launching stream around
+# The dominant kernels, each timed alone: HIP events on the launching stream around
 # mlmc_paths with no per-path outputs, which launches exactly the level kernel of
-# mlmc_level_ex (same instance and grid) without the two kernels of the chunk reduction
+# mlmc_level_ex (same instance and grid) without the two kernels of the chunk reduction.
+# Per coupled path-step, counted in the AMD assembly of the kernels' step loop (one trip =
+# one Philox call: four fine steps of a lane's path, two packed paths in binary16; the
+# branch of the deep cells of the exact variable, taken with probability 2^-11, excluded):
+#   slots  weighted issue cost of the loop's VALU instructions (the weights above)
+#   valu   VALU instructions; rocprofv3's SQ_INSTS_VALU per launch agrees within 2% (the
+#          rest is the rows' set-up and reduction)
+#   flops  floating-point operations by precision (an FMA counts 2, a packed binary16
+#          operation 2 or 4)
 ROOFLINE_KERNELS = {
     "fp32": dict(precision="MLMC_FP32", mode="MLMC_NESTED_PWL16", kahan=1, level=10, n_paths=2 ** 20,
-                 alg_ops=ALG_OPS_PER_STEP,
+                 slots=38.25, valu=52.25, flops={"f64": 24.5, "f32": 14.5},
                  kernel="level_kernel<FP32, PWL16, nested, Kahan> at level 10 (2^20 paths x 1024 steps)"),
     "fp16": dict(precision="MLMC_FP16", mode="MLMC_NESTED_CUBIC16", kahan=1, level=6, n_paths=2 ** 24,
-                 alg_ops=None,
+                 slots=41.75, valu=52.0, flops={"f64": 24.5, "f32": 1.0, "f16": 18.5},
                  kernel="level_kernel<FP16, CUBIC16, nested, Kahan> at level 6 (2^24 paths x 64 steps)"),
 }
-# floating-point operations per launch of each kernel by precision, from rocprofv3's
-# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F16,F32,F64} counters (64 lanes x (ADD + MUL + TRANS +
-# 2 FMA) per wave instruction; a packed binary16 instruction counts twice), valid for the
-# kernel sources hashed below (None: not taken for these sources)
-FLOPS_PER_LAUNCH = {"fp32": None, "fp16": None}
-FLOPS_SOURCES_SHA256 = None
-# HBM bytes per level-10 launch of that kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-# (scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = (210.9375 * 2.0 + 1024.0) * 1024  # profiles/level_kernel_nested_fp32_pwl16_call_l10_2p20.md
-TRAFFIC_SOURCES_SHA256 = "d22d7bed81db7971a6a06449ff72bc16ddbed1d2ccb6b80446af26d221ac7542"
-KERNEL_SOURCES = ("level_kernel.h", "level_launch.h", "icdf.h", "philox.h", "mlp.h", "internal.h", "level_f32.hip",
-                  "level_f16.hip", "icdf_exact_coeffs.h", "abi.cpp")  # abi.cpp: the launch grid
+# the sources and build flags the counts above were taken from (sha256 of ISA_SOURCES)
+ISA_SOURCES_SHA256 = "e664f3669b2d02bae6bb50d574e02b87a09fbad29af0b74b58902bdc639ac650"
+# HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB;
+# scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": (218.938 * 2.0 + 1024.0) * 1024, "fp16": (3311.94 * 2.0 + 14336.0) * 1024}
+TRAFFIC_SOURCES_SHA256 = "ac6912eb52f64947be02b6ef2734c7f686efd37e8777fef383352af6e369ddc6"
+# what a kernel's instructions depend on: its sources and the build flags
+ISA_SOURCES = ("csrc/level_kernel.h", "csrc/level_launch.h", "csrc/icdf.h", "csrc/philox.h", "csrc/mlp.h",
+               "csrc/internal.h", "csrc/level_f32.hip", "csrc/level_f16.hip", "csrc/icdf_exact_coeffs.h", "build.py")
+# and its memory traffic besides: the launch grid (the number of partial rows)
+KERNEL_SOURCES = ISA_SOURCES + ("csrc/abi.cpp",)
 
 
-def kernel_sources_sha256():
+def sources_sha256(names):
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2012_09739_amd", "csrc", name), "rb") as f:
+    for name in names:
+        with open(os.path.join(ROOT, "paper_2012_09739_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def traffic_bytes():
+def kernel_sources_sha256():
+    return sources_sha256(KERNEL_SOURCES)
+
+
+def traffic_bytes(key):
     """The counter-derived traffic if the kernel sources are unchanged since it was taken."""
-    if TRAFFIC_BYTES_PER_LAUNCH is None or kernel_sources_sha256() != TRAFFIC_SOURCES_SHA256:
+    if TRAFFIC_BYTES_PER_LAUNCH.get(key) is None or kernel_sources_sha256() != TRAFFIC_SOURCES_SHA256:
         return None
-    return TRAFFIC_BYTES_PER_LAUNCH
+    return TRAFFIC_BYTES_PER_LAUNCH[key]
 
 
-REPORT_LEGS = ("plain", "fp16", "batch", "mlp", "sweep", "adaptive", "milstein", "pconst", "valu_rates")
+REPORT_LEGS = ("plain", "fp16", "batch", "mlp", "sweep", "adaptive", "milstein", "pconst", "marginal", "valu_rates")
 # opcodes of the issue-rate probes (include/valu_rates.h order)
 VALU_OPS = ("v_fma_f64", "v_mul_f64", "v_add_f64", "v_fma_f32", "v_mul_f32", "v_pk_fma_f16", "v_pk_mul_f16",
             "v_fma_f16", "v_bitop3_b32 (xor3)", "v_add_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_ffbh_u32",
@@ -309,9 +313,9 @@ def kernel_ms(M, torch, args, reps=10, warm=2):
 
 
 def roofline_block(M, torch, key):
-    """Issue roofline of one dominant kernel (alu bound): algorithmic binary64-equivalent VALU
-    slots per launch over its measured duration against the 39.32 T slots/s peak, with the
-    counter-derived FLOP/s of each precision against its vector peak."""
+    """Issue roofline of one dominant kernel (alu bound): VALU issue slots per launch over its
+    measured duration against the 39.32 T slots/s peak, with the FLOP/s of each precision
+    against its vector peak (counts valid for the hashed kernel sources, else null)."""
     k = ROOFLINE_KERNELS[key]
     call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
     args = M.level_args(call, k["level"], k["n_paths"], getattr(M, k["precision"]), getattr(M, k["mode"]),
@@ -319,24 +323,19 @@ def roofline_block(M, torch, key):
     times = kernel_ms(M, torch, args)
     ms = sum(times) / len(times)
     steps = k["n_paths"] << k["level"]
-    blk = {"bound": "alu", "peak": PEAK_VALU_TOPS, "unit": "T binary64-equivalent VALU lane-ops/s",
+    rate = steps / (ms * 1e-3)
+    fresh = ISA_SOURCES_SHA256 == sources_sha256(ISA_SOURCES)
+    blk = {"bound": "alu", "peak": PEAK_VALU_TOPS, "unit": "T VALU issue slots/s",
            "kernel": k["kernel"], "kernel_ms": ms, "kernel_ms_min": min(times), "launches_timed": len(times),
-           "coupled_path_steps_per_s": steps / (ms * 1e-3), "alg_ops_per_path_step": k["alg_ops"],
-           "traffic": traffic_bytes() if key == "fp32" else None}
-    if k["alg_ops"] is not None:
-        achieved = k["alg_ops"] * steps / (ms * 1e-3) / 1e12
-        blk.update(achieved=achieved, frac=achieved / PEAK_VALU_TOPS)
+           "coupled_path_steps_per_s": rate, "traffic": traffic_bytes(key)}
+    if fresh:
+        achieved = k["slots"] * rate / 1e12
+        blk.update(achieved=achieved, frac=achieved / PEAK_VALU_TOPS, slots_per_path_step=k["slots"],
+                   valu_instr_per_path_step=k["valu"],
+                   flops={p: {"tflops": f * rate / 1e12, "peak_tflops": PEAK_TFLOPS[p],
+                              "frac": f * rate / 1e12 / PEAK_TFLOPS[p]} for p, f in k["flops"].items()})
     else:
-        blk.update(achieved=None, frac=None)
-    fl = FLOPS_PER_LAUNCH.get(key)
-    if fl is not None and FLOPS_SOURCES_SHA256 == kernel_sources_sha256():
-        per = {p: {"tflops": fl[p] / (ms * 1e-3) / 1e12, "peak_tflops": PEAK_TFLOPS[p],
-                   "frac": fl[p] / (ms * 1e-3) / 1e12 / PEAK_TFLOPS[p]} for p in fl}
-        blk["flops"] = per
-        # the VALU time the floating-point work alone would take at each precision's peak
-        blk["flop_time_frac"] = sum(v["frac"] for v in per.values())
-    else:
-        blk["flops"] = None
+        blk.update(achieved=None, frac=None, slots_per_path_step=None, valu_instr_per_path_step=None, flops=None)
     return blk
 
 
@@ -630,6 +629,23 @@ def reports(M, E, torch, legs=REPORT_LEGS):
                            var(plain_rows, 0), cost(plain_rows), var(a_rows, 0), cost(a_rows), var(n_rows, 1),
                            cost(n_rows))}
         rep["pconst4096_vs_dyadic_call_levels0to10_2p20"] = pc
+    if "marginal" in legs:
+        # marginal device cost per coupled path-step of the level kernel alone, (t(4n) - t(n)) /
+        # (3 n 2^l), at the coarse levels (where the MLMC allocation puts most samples) and at
+        # level 10, from HIP events around mlmc_paths
+        marg = {}
+        for tag, prec, mode, k in (("nested_fp32_pwl16_kahan", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1),
+                                   ("nested_fp16_cubic16_kahan", M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1),
+                                   ("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0)):
+            row = {}
+            for l in (0, 1, 2, 3, 10):
+                n = 2 ** 20 if l < 10 else 2 ** 18
+                t1 = sum(kernel_ms(M, torch, M.level_args(call, l, n, prec, mode, k, SEED))) / 10
+                t4 = sum(kernel_ms(M, torch, M.level_args(call, l, 4 * n, prec, mode, k, SEED))) / 10
+                row["level_%d" % l] = {"ms_n": t1, "ms_4n": t4, "n": n,
+                                       "ps_per_path_step": (t4 - t1) * 1e9 / (3 * n * 2 ** l)}
+            marg[tag] = row
+        rep["marginal_cost_per_path_step"] = marg
     if "valu_rates" in legs:
         rep["valu_issue_rates"] = valu_rates()
     np.seterr(all="ignore")

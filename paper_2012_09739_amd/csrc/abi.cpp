@@ -256,14 +256,12 @@ int device_state(DevState** out) {
                 const double* v = kRows + k * (kExactDeg + 1);
                 if (k < kDeepRows) {
                     for (int j = 0; j < kRowLen; ++j) h.deep[k][j] = j <= kExactDeg ? v[j] : 0.0;
-                } else {  // coefficients 5 and 6 of a top cell are binary32 values (exact conversion)
+                } else {  // (coefficients 5 and 6 of a top cell are binary32 values)
                     const int i = k - kDeepRows;
                     h.lds.top.c01[i] = make_double2(v[0], v[1]);
                     h.lds.top.c23[i] = make_double2(v[2], v[3]);
-                    const float hi2[2] = {(float)v[5], (float)v[6]};
-                    double packed;
-                    std::memcpy(&packed, hi2, sizeof packed);
-                    h.lds.top.c456[i] = make_double2(packed, v[4]);
+                    h.lds.top.c45[i] = make_double2(v[4], v[5]);
+                    h.lds.top.c6[i] = make_double2(v[6], 0.0);
                 }
             }
             if ((e = hipMalloc(&st.exact_tab, sizeof h)) != hipSuccess) return hip_fail(e, "hipMalloc");

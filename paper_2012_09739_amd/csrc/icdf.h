@@ -66,13 +66,14 @@ __device__ __forceinline__ double sgpr_const(double c) {
 // Table of the exact variable: the 7 coefficients of G on each cell of y.  Cell k has the
 // key kKeyMin + k, the key of y being its biased exponent and five leading mantissa bits
 // (the upper word shifted right by 15).  The cells of y >= 2^-10 (the top cells) sit in LDS
-// as three arrays of 16-byte entries -- (c0, c1), (c2, c3) and (binary32 c5, binary32 c6,
-// c4) -- so a lane reads its cell with three 16-byte loads from one address plus fixed
-// offsets.  The deep cells below 2^-10 stay in global memory as 64-byte rows of binary64
-// coefficients and are read only by lanes whose y falls there (probability 2^-11 per word).
+// as four arrays of 16-byte entries -- (c0, c1), (c2, c3), (c4, c5) and (c6, unused) -- so a
+// lane reads its cell with loads from one address plus fixed offsets and no conversion (c5
+// and c6 are binary32 values, stored widened).  The deep cells below 2^-10 stay in global
+// memory as 64-byte rows of binary64 coefficients and are read only by lanes whose y falls
+// there (probability 2^-11 per word).
 constexpr int kCellBits = MLMC_EXACT_CELL_BITS;
 constexpr int kExactDeg = MLMC_EXACT_DEG;
-static_assert(kExactDeg == 6, "three 16-byte entries per top cell");
+static_assert(kExactDeg == 6, "four 16-byte entries per top cell");
 constexpr int kRowLen = 8;
 constexpr uint32_t kKeyMin = (uint32_t)MLMC_EXACT_E_MIN << kCellBits;
 constexpr int kExactRows = MLMC_EXACT_ROWS;
@@ -85,7 +86,8 @@ constexpr int kDeepRows = kExactRows - kTopCells;
 struct ExactCols {
     double2 c01[kTopCells];
     double2 c23[kTopCells];
-    double2 c456[kTopCells];  // (the bits of the binary32 pair (c5, c6), c4)
+    double2 c45[kTopCells];
+    double2 c6[kTopCells];  // (c6, 0)
 };
 // what kernels stage into LDS: the top cells, then the log cells (only for the learned variable)
 struct ExactLds {
@@ -128,11 +130,9 @@ __device__ __forceinline__ double icdf_G(double y, const ExactCols* __restrict__
     const double c = __hiloint2double((int)((key << (20 - kCellBits)) | kHalf), 0);
     const double t = y - c;
     const uint32_t k = (key > kKeyTop ? key : kKeyTop) - kKeyTop;
-    const double2 p01 = top->c01[k], p23 = top->c23[k];
-    double2 p4 = top->c456[k];
-    asm volatile("" : "+v"(p4.x), "+v"(p4.y));  // one 16-byte load, not two 8-byte ones
-    const float2 f56 = __builtin_bit_cast(float2, p4.x);
-    double g = cell_poly({p01.x, p01.y, p23.x, p23.y, p4.y, (double)f56.x, (double)f56.y}, t);
+    const double2 p01 = top->c01[k], p23 = top->c23[k], p45 = top->c45[k];
+    const double p6 = top->c6[k].x;
+    double g = cell_poly({p01.x, p01.y, p23.x, p23.y, p45.x, p45.y, p6}, t);
     // g is final here for the top lanes: the deep branch below then neither merges its loads
     // with the LDS ones (a flat load) nor shares this Horner chain through copies
     asm volatile("" : "+v"(g));
@@ -290,6 +290,40 @@ __device__ __forceinline__ __half icdf_dyadic_f16(uint32_t word, const __half* _
         q = __hadd(q, c[i]);
     }
     return __ushort_as_half((unsigned short)(__half_as_ushort(q) ^ (p.sign >> 16)));
+}
+
+// The binary16 variables of two words as one pair (the two packed paths of a lane): the same
+// values as two icdf_dyadic_f16 calls, with both coordinates narrowed by one conversion of the
+// pair and both signs applied by one 32-bit xor.
+template <int DEG>
+__device__ __forceinline__ __half2 icdf_dyadic_f16x2(uint32_t w0, uint32_t w1, const __half* __restrict__ tab) {
+    const DyadicPos p0 = dyadic_locate(w0), p1 = dyadic_locate(w1);
+    // R_16(R_32(T) 2^-31) for both in one conversion (the scaling by 2^-31 is exact, T >= 1;
+    // v_cvt_pk_f16_f32 rounds to nearest like the scalar conversion).  Written as the
+    // instruction itself: the compiler would otherwise fuse each product and its narrowing
+    // into a mixed-precision multiply-add, at twice the issue cost of the pair.
+    const float a0 = (float)p0.T * 0x1p-31f, a1 = (float)p1.T * 0x1p-31f;
+    uint32_t tp;
+    asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(tp) : "v"(a0), "v"(a1));
+    const _Float16 t0 = __builtin_bit_cast(_Float16, (uint16_t)tp);
+    const _Float16 t1 = __builtin_bit_cast(_Float16, (uint16_t)(tp >> 16));
+    const _Float16* c0 = (const _Float16*)(tab + p0.row * (DEG + 1));
+    const _Float16* c1 = (const _Float16*)(tab + p1.row * (DEG + 1));
+    _Float16 q0 = c0[DEG], q1 = c1[DEG];
+#pragma unroll
+    for (int i = DEG - 1; i >= 0; --i) {
+        q0 = q0 * t0;  // separately rounded (the build does not contract)
+        q0 = q0 + c0[i];
+        q1 = q1 * t1;
+        q1 = q1 + c1[i];
+    }
+    // bit 31 of w0 to bit 15 and bit 31 of w1 to bit 31 (bytes 3 of each, then the sign bits)
+    const uint32_t sgn = __builtin_amdgcn_perm(w1, w0, 0x070C030Cu) & 0x80008000u;
+    const uint32_t q = (uint32_t)__builtin_bit_cast(uint16_t, q0) | ((uint32_t)__builtin_bit_cast(uint16_t, q1) << 16);
+    const uint32_t bits = q ^ sgn;
+    __half2 z;
+    __builtin_memcpy(&z, &bits, sizeof z);
+    return z;
 }
 
 // ---- piecewise-constant variable (table lookup) ------------------------------------------

@@ -306,18 +306,15 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
                 if (!coarse) zb_prev = z;
             }
             if constexpr (kNeedApprox && PREC == MLMC_FP16) {
-                __half z0, z1;
+                __half2 z;
                 if constexpr (RV == MLMC_RV_MLP) {
-                    z0 = __float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw));
-                    z1 = __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw));
+                    z = __halves2half2(__float2half_rn(icdf_mlp_f32(r[0].w[i], mlpw)),
+                                       __float2half_rn(icdf_mlp_f32(r[1].w[i], mlpw)));
                 } else if constexpr (RV == MLMC_RV_PCONST4096) {
-                    z0 = icdf_pconst_f16(r[0].w[i], s_tab16);
-                    z1 = icdf_pconst_f16(r[1].w[i], s_tab16);
+                    z = __halves2half2(icdf_pconst_f16(r[0].w[i], s_tab16), icdf_pconst_f16(r[1].w[i], s_tab16));
                 } else {
-                    z0 = icdf_dyadic_f16<DEG>(r[0].w[i], s_tab16);
-                    z1 = icdf_dyadic_f16<DEG>(r[1].w[i], s_tab16);
+                    z = icdf_dyadic_f16x2<DEG>(r[0].w[i], r[1].w[i], s_tab16);
                 }
-                const __half2 z = __halves2half2(z0, z1);
                 if constexpr (kKahan) {
                     em_step_kahan_h2<SCHEME>(Xf2, cf2, z, ca2, cb2, cm2, one2);
                     if (coarse) em_step_kahan_h2<SCHEME>(Xc2, cc2, __hadd2(z2_prev, z), cac2, cb2, cm2, two2);
