@@ -4,7 +4,7 @@
 // about u = 1/2 (exactly zero mean) and bounded for 32-bit words.  Deployed form (the
 // training form's hard tanh h = min(max(z, -1), 1) rewritten with c = (h + 1) / 2, so every
 // activation is the clamp to [0, 1] of the instruction that forms its argument):
-//   2u = R_32(2 xm + 1) 2^-32, r = sqrt(-2 ln 2u), x = R_16(r C - 1), C = R_32(1 / 3.4),
+//   2u = R_32(2 xm + 1) 2^-32, r = sqrt(-2 ln 2u), x = R_16(R_32(r C - 1)), C = R_32(1 / 3.4),
 //   c1 = clamp01(A1 x + a1)            (packed binary16 fused multiply-add, clamped),
 //   c2 = clamp01(R_16(A2 c1 + a2))     (binary16 matrix instruction, binary32 accumulation,
 //                                       rounded to binary16 and clamped in one conversion),
@@ -111,8 +111,11 @@ __device__ __forceinline__ float icdf_mlp_f32(uint32_t word, const float* __rest
     const float two_u = (float)(2u * xm + 1u) * 0x1p-32f;         // R_32(2 xm + 1), scaled exactly
     const float r = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(two_u) * -1.38629436111989061f);  // -2 ln 2
     const float x = __builtin_fmaf(r, (float)(1.0 / 3.4), -1.0f);
-    const uint32_t x16 = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
-    const float q = mlp_eval_wave(x16 | (x16 << 16), W) - r;
+    // R_16(x) in both halves with one conversion (written as the instruction: the compiler
+    // would fuse the fma and the narrowing into a mixed-precision fma, then duplicate the half)
+    uint32_t x16x2;
+    asm("v_cvt_pk_f16_f32 %0, %1, %1" : "=v"(x16x2) : "v"(x));
+    const float q = mlp_eval_wave(x16x2, W) - r;
     return apply_sign(q, word & 0x80000000u);
 }
 
