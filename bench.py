@@ -66,11 +66,11 @@ ROOFLINE_KERNELS = {
                  kernel="level_kernel<FP16, CUBIC16, nested, Kahan> at level 6 (2^24 paths x 64 steps)"),
 }
 # the sources and build flags the counts above were taken from (sha256 of ISA_SOURCES)
-ISA_SOURCES_SHA256 = "e664f3669b2d02bae6bb50d574e02b87a09fbad29af0b74b58902bdc639ac650"
+ISA_SOURCES_SHA256 = "614cb7327aba0e93e0c1e037ab8117ce200241fd05b29661fda74e5d2789399a"
 # HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB;
 # scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
 TRAFFIC_BYTES_PER_LAUNCH = {"fp32": (218.938 * 2.0 + 1024.0) * 1024, "fp16": (3311.94 * 2.0 + 14336.0) * 1024}
-TRAFFIC_SOURCES_SHA256 = "ac6912eb52f64947be02b6ef2734c7f686efd37e8777fef383352af6e369ddc6"
+TRAFFIC_SOURCES_SHA256 = "e5cdd2cf5be2e8817b832c36394ad97112bb951bfbcab2d1cc001d2d5df49382"
 # what a kernel's instructions depend on: its sources and the build flags
 ISA_SOURCES = ("csrc/level_kernel.h", "csrc/level_launch.h", "csrc/icdf.h", "csrc/philox.h", "csrc/mlp.h",
                "csrc/internal.h", "csrc/level_f32.hip", "csrc/level_f16.hip", "csrc/icdf_exact_coeffs.h", "build.py")

@@ -278,6 +278,15 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
                 }
             }
         }
+        // the learned variable of the call's four words together (binary64/binary32 paths,
+        // levels >= 2): their matrix-instruction chains interleave
+        float zmlp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (RV == MLMC_RV_MLP && PREC != MLMC_FP16 && !SHORT) {
+            float za[2], zb[2];
+            icdf_mlp_f32_k<2>(r[0].w, mlpw, za);
+            icdf_mlp_f32_k<2>(r[0].w + 2, mlpw, zb);
+            zmlp[0] = za[0]; zmlp[1] = za[1]; zmlp[2] = zb[0]; zmlp[3] = zb[1];
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             // only levels 0 and 1 stop inside a call, and they run as SHORT instances
@@ -295,7 +304,9 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
                 }
             }
             if constexpr (kNeedApprox && PREC != MLMC_FP16) {
-                const AT z = approx_rv<RV, DEG, AT, PREC>(r[0].w[i], s_tab, mlpw);
+                AT z;
+                if constexpr (RV == MLMC_RV_MLP && !SHORT) z = (AT)zmlp[i];
+                else z = approx_rv<RV, DEG, AT, PREC>(r[0].w[i], s_tab, mlpw);
                 if constexpr (kKahan) {
                     em_step_kahan<SCHEME, AT>(Xfb, cfb, z, ca_b, cb_b, cm_b, one_b, rnd);
                     if (coarse) em_step_kahan<SCHEME, AT>(Xcb, ccb, rnd(zb_prev + z), cac_b, cb_b, cm_b, two_b, rnd);

@@ -105,6 +105,67 @@ __device__ __forceinline__ float mlp_eval_wave(uint32_t x16x2, const float* __re
     return y[0];
 }
 
+// y for K inputs per lane at once (the K variables of one Philox call): the same operations as
+// K mlp_eval_wave calls, ordered block by block so that the K independent chains of matrix
+// instructions interleave and hide each other's latency.
+template <int K>
+__device__ __forceinline__ void mlp_eval_wave_k(const uint32_t (&x16x2)[K], const float* __restrict__ W,
+                                                float (&out)[K]) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t c = lane & 15u, g = lane >> 4;
+    const float4 l1 = *(const float4*)(W + kPkL1 + 4 * g);
+    const mlp_h2 w1a = __builtin_bit_cast(mlp_h2, l1.x), w1b = __builtin_bit_cast(mlp_h2, l1.y);
+    const mlp_h2 b1a = __builtin_bit_cast(mlp_h2, l1.z), b1b = __builtin_bit_cast(mlp_h2, l1.w);
+    const mlp_h4 w2 = __builtin_bit_cast(mlp_h4, *(const float2*)(W + kPkA2 + 2 * lane));
+    const mlp_f4 b2 = __builtin_bit_cast(mlp_f4, *(const float4*)(W + kB2 + 4 * g));
+    const float* a3 = W + kPkA3 + 2 * (4 * (c >> 2) + g);
+    const mlp_f4 y0 = __builtin_bit_cast(mlp_f4, *(const float4*)(W + kPkB3));
+    const mlp_h2 zero = {(_Float16)0.0f, (_Float16)0.0f}, one = {(_Float16)1.0f, (_Float16)1.0f};
+    mlp_f4 y[K];
+#pragma unroll
+    for (int v = 0; v < K; ++v) y[v] = y0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const mlp_h4 w3 = __builtin_bit_cast(mlp_h4, *(const float2*)(a3 + 32 * b));
+        mlp_f4 d[K];
+#pragma unroll
+        for (int v = 0; v < K; ++v) {
+            const mlp_h2 xb = __builtin_bit_cast(mlp_h2, (uint32_t)__shfl((int)x16x2[v], 16 * b + (int)c, kWave));
+            const mlp_h2 h01 = mlp_unit_pair(w1a, xb, b1a), h23 = mlp_unit_pair(w1b, xb, b1b);
+            const mlp_h4 bop = {h01[0], h01[1], h23[0], h23[1]};
+            d[v] = __builtin_amdgcn_mfma_f32_16x16x16f16(w2, bop, b2, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < K; ++v) {
+            mlp_h2 c01 = {(_Float16)d[v][0], (_Float16)d[v][1]}, c23 = {(_Float16)d[v][2], (_Float16)d[v][3]};
+            c01 = __builtin_elementwise_min(__builtin_elementwise_max(c01, zero), one);
+            c23 = __builtin_elementwise_min(__builtin_elementwise_max(c23, zero), one);
+            const mlp_h4 c2 = {c01[0], c01[1], c23[0], c23[1]};
+            y[v] = __builtin_amdgcn_mfma_f32_16x16x16f16(w3, c2, y[v], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < K; ++v) out[v] = y[v][0];
+}
+
+// The learned variables of K words per lane (all 64 lanes together), as icdf_mlp_f32 each.
+template <int K>
+__device__ __forceinline__ void icdf_mlp_f32_k(const uint32_t* word, const float* __restrict__ W, float (&z)[K]) {
+    uint32_t x16x2[K];
+    float r[K], y[K];
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+        const uint32_t xm = word[v] ^ (uint32_t)((int32_t)word[v] >> 31);
+        const float two_u = (float)(2u * xm + 1u) * 0x1p-32f;
+        r[v] = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(two_u) * -1.38629436111989061f);
+        const float x = __builtin_fmaf(r[v], (float)(1.0 / 3.4), -1.0f);
+        asm("v_cvt_pk_f16_f32 %0, %1, %1" : "=v"(x16x2[v]) : "v"(x));
+    }
+    mlp_eval_wave_k<K>(x16x2, W, y);
+#pragma unroll
+    for (int v = 0; v < K; ++v) z[v] = apply_sign(y[v] - r[v], word[v] & 0x80000000u);
+}
+
 // The learned approximate variable of every lane's word (all 64 lanes together).
 __device__ __forceinline__ float icdf_mlp_f32(uint32_t word, const float* __restrict__ W) {
     const uint32_t xm = word ^ (uint32_t)((int32_t)word >> 31);  // ~word on the upper half

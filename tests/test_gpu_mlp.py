@@ -114,15 +114,17 @@ def test_inference_matches_oracle_on_seeded_weights():
     np.testing.assert_array_equal(zm, -gpu_icdf(words, M.MLMC_RV_MLP, M.MLMC_FP32))
 
 
-def test_nested_mlp_paths_match_oracle():
+@pytest.mark.parametrize("level", [0, 1, 4])
+def test_nested_mlp_paths_match_oracle(level):
     """Per-path payoffs of the nested estimator with the learned variable: the exact pair to
     1e-13, the approximate pair to the binary32 bar plus the oracle's first-order bound on
-    what the two correct roundings of each variable's second-layer sums can change."""
+    what the two correct roundings of each variable's second-layer sums can change (levels 0
+    and 1: the shared-call instance; level 4: four variables per call evaluated together)."""
     torch = torch_cuda()
     p = W.mlp_initial_params(5) + np.random.default_rng(6).normal(0, 0.1, mlp.N_PARAMS)
     M.mlmc_mlp_load(dev(p))
     q = mlp.deployed(p.astype(np.float32))
-    n, level = 1000, 4
+    n = 1000
     g = gpu_paths(W.GBM_CALL, level, n, M.MLMC_FP32, M.MLMC_RV_MLP, True, 1, 8)
     o = mlmc.level_paths(level, np.arange(n), W.GBM_CALL, rv_mode=mlmc.RV_MLP, precision=fp.FP32, nested=True,
                          kahan=True, seed=8, stream=1, mlp_params=q)

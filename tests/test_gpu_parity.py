@@ -136,6 +136,49 @@ def test_nested_fp16_per_path(level, rv, kahan):
     assert np.all(close(g["xf_tilde"], o["Xf_tilde"], 1e-13))
 
 
+@pytest.mark.parametrize("offset", [0, 1, 2, 3, 2 ** 32 - 1003])
+@pytest.mark.parametrize("level", [0, 1])
+def test_coarse_levels_share_calls_at_any_path_offset(level, offset):
+    """Levels 0 and 1 draw one Philox call per 4 / 2^l consecutive paths; a slice that starts
+    inside a group (offset not a multiple of the group) takes the words of two calls per lane.
+    Nested binary32 (Kahan) and packed binary16 paths and the plain binary64 ones, per path, with
+    a ragged count, against the oracle's words of the same global paths."""
+    n = 1000
+    sde = W.NESTED_FP32["sde"]
+    paths = np.arange(offset, offset + n)
+    g = gpu_paths(sde, level, n, M.MLMC_FP32, M.MLMC_RV_PWL16, True, 1, 5, path_offset=offset)
+    o = mlmc.level_paths(level, paths, sde, rv_mode=mlmc.RV_PWL, precision=fp.FP32, nested=True, kahan=True,
+                         seed=5, stream=1)
+    assert np.all(close(g["pf_hat"], o["Pf_hat"], 1e-13))
+    np.testing.assert_array_equal(g["pf_bar"], o["Pf_bar"])     # binary32 emulated exactly
+    np.testing.assert_array_equal(g["pc_bar"], o["Pc_bar"])
+    g16 = gpu_paths(sde, level, n, M.MLMC_FP16, mlmc.RV_CUBIC, True, 1, 5, path_offset=offset)
+    o16 = mlmc.level_paths(level, paths, sde, rv_mode=mlmc.RV_CUBIC, precision=fp.FP16, nested=True, kahan=True,
+                           seed=5, stream=1)
+    np.testing.assert_array_equal(g16["pf_bar"], o16["Pf_bar"])
+    np.testing.assert_array_equal(g16["pc_bar"], o16["Pc_bar"])
+    assert np.all(close(g16["pf_hat"], o16["Pf_hat"], 1e-13))
+    g64 = gpu_paths(sde, level, n, M.MLMC_FP64, 0, False, 0, 5, path_offset=offset)
+    o64 = mlmc.level_paths(level, paths, sde, rv_mode=0, precision=fp.FP64, nested=False, kahan=False, seed=5)
+    assert np.all(close(g64["pf_hat"], o64["Pf_hat"], 1e-13))
+    assert np.all(close(g64["pc_hat"], o64["Pc_hat"], 1e-13))
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_approx_only_coarse_levels_per_path(level):
+    # every variant runs levels 0 and 1 through the shared-call instance, the approximate-only
+    # ones included
+    n = 777
+    sde = W.GBM
+    for precision, rv in ((M.MLMC_FP32, mlmc.RV_PWL), (M.MLMC_FP16, mlmc.RV_CUBIC)):
+        g = gpu_paths(sde, level, n, precision, rv, False, 1, 17, path_offset=6)
+        o = mlmc.level_paths(level, np.arange(6, 6 + n), sde, rv_mode=rv, precision=precision, nested=False,
+                             kahan=True, seed=17)
+        np.testing.assert_array_equal(g["pf_bar"], o["Pf_bar"])
+        np.testing.assert_array_equal(g["pc_bar"], o["Pc_bar"])
+        assert np.all(np.isnan(g["pf_hat"]))
+
+
 @pytest.mark.parametrize("precision,rv", [(M.MLMC_FP64, mlmc.RV_PWL), (M.MLMC_FP64, mlmc.RV_CUBIC),
                                           (M.MLMC_FP32, mlmc.RV_CUBIC)])
 def test_approx_only_per_path(precision, rv):
