@@ -494,7 +494,9 @@ def reports(M, E, torch, legs=REPORT_LEGS):
             "path_steps_per_s": steps / ms * 1e3,
             "standalone_same_work_ms": sum(stand), "standalone_ms_by_level": stand,
             "rate_over_standalone": sum(stand) / ms,
-            "autotuned": [best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level],
+            "autotuned": {"waves_per_cu": best.waves_per_cu, "task_steps": best.task_steps,
+                          "priority_level": best.priority_level, "coop_level": best.coop_level,
+                          "block_waves": best.block_waves},
             "wave_slot_utilisation": sum(wave_s) / (resident * ms * 1e-3),
             "cost_per_sample_s_by_level": [float(np.mean(per_level[l])) for l in sorted(per_level)]}
 

@@ -260,15 +260,16 @@ typedef struct {
 
 /* launch shape of a batch (0 in a field selects the default or the autotuned value) */
 typedef struct {
-    int32_t waves_per_cu;    /* wavefronts per CU of the persistent grid (8-wave blocks;  */
-                             /* the count is rounded down to whole blocks): 4..32         */
+    int32_t waves_per_cu;    /* wavefronts per CU of the persistent grid (rounded down to */
+                             /* whole blocks): 4..32, at least one block                  */
     int32_t task_steps;      /* fine steps per task at level 0 (tasks of level l hold      */
                              /* max(1, task_steps >> l) chunks): 1..2^20                 */
     int32_t priority_level;  /* tasks of level >= this run at raised wave priority; 25=off */
     int32_t coop_level;      /* binary32 items of level >= this (2..25; 25 = off) run each   */
-                             /* chunk on a whole 8-wave block: seven waves draw the       */
-                             /* variables of the next 28 steps into LDS while one wave    */
-                             /* advances the paths (same operations, same bits)           */
+                             /* chunk on a whole block: its other waves draw the variables */
+                             /* of the next 4 (block_waves - 1) steps into LDS while one   */
+                             /* wave advances the paths (same operations, same bits)       */
+    int32_t block_waves;     /* wavefronts per block: 8 or 4                               */
 } mlmc_batch_cfg_t;
 
 typedef struct mlmc_batch mlmc_batch_t; /* opaque plan (device task list + captured graph) */

@@ -84,20 +84,28 @@ __global__ void batch_reset(uint32_t* counter, unsigned long long* ticks, uint32
     for (uint32_t k = i; k < n_items; k += gridDim.x * blockDim.x) ticks[k] = 0ull;
 }
 
-constexpr int kBatchBlock = 512;                         // eight waves
-constexpr int kCoopProducers = kBatchBlock / kWave - 1;  // waves 1..7 of a block
-constexpr int kCoopSteps = 4 * kCoopProducers;            // fine steps per phase: one Philox call per producer
+// Blocks of WAVES = 8 (the default) or 4 wavefronts; a cooperative chunk's producers are
+// waves 1 .. WAVES - 1, each drawing one Philox call (four fine steps) per phase.
+constexpr int kDefaultBlockWaves = 8;
+template <int WAVES>
+struct Coop {
+    static constexpr int kProducers = WAVES - 1;
+    static constexpr int kSteps = 4 * kProducers;  // fine steps per phase
+};
 
 // One cooperative chunk of a nested binary32 item (n_steps >= 4, a multiple of 4) run by
-// the whole block.  Phase f covers fine steps [28 f, 28 f + 28): producer wave p draws
-// Philox call 7 f + p - 1 and writes its four exact (binary64) and approximate (binary32)
-// variables into ring slot f & 1; the consumer, wave 0, reads slot f & 1 while the
-// producers fill slot (f + 1) & 1, and a barrier closes every phase (the same number of
-// barriers in every wave).  The consumer's updates and payoff terms are those of run_chunk
-// for this variant, in the same order.
-template <int RV, bool KAHAN>
+// the whole block of WAVES waves, P = WAVES - 1 of them producers.  Phase f covers fine steps
+// [4 P f, 4 P f + 4 P): producer wave p draws Philox call P f + p - 1 and writes its four exact
+// (binary64) and approximate (binary32) variables into ring slot f & 1; the consumer, wave 0,
+// reads slot f & 1 while the producers fill slot (f + 1) & 1, and a barrier closes every phase
+// (the same number of barriers in every wave).  The consumer's updates and payoff terms are
+// those of the single-wave code for this variant, in the same order.
+template <int RV, bool KAHAN, int WAVES>
 __device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const float* s_tab, const ExactLds* s_ex,
-                               double (*ring_x)[kCoopSteps][kWave], float (*ring_b)[kCoopSteps][kWave]) {
+                               double (*ring_x)[Coop<WAVES>::kSteps][kWave],
+                               float (*ring_b)[Coop<WAVES>::kSteps][kWave]) {
+    constexpr int kCoopProducers = Coop<WAVES>::kProducers;
+    constexpr int kCoopSteps = Coop<WAVES>::kSteps;
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
     const uint32_t wave = threadIdx.x / kWave;
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -182,8 +190,8 @@ __device__ void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const flo
     store_row(acc, lane, prm.partials + chunk * kPartial);
 }
 
-template <int RV>
-__global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
+template <int RV, int WAVES>
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(const LevelParams* __restrict__ params, const int* __restrict__ variant,
                                                     const uint4* __restrict__ tasks, uint32_t n_tasks,
                                                     const uint2* __restrict__ coop, uint32_t n_coop,
                                                     uint32_t* __restrict__ counter, const float* __restrict__ tab32,
@@ -193,8 +201,8 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))
     __shared__ float s_tab32[kTableRowsDev * 4];
     __shared__ __half s_tab16[kTableRowsDev * 4];
     __shared__ __align__(16) unsigned char s_ex_raw[sizeof(ExactCols)];
-    __shared__ double ring_x[2][kCoopSteps][kWave];
-    __shared__ float ring_b[2][kCoopSteps][kWave];
+    __shared__ double ring_x[2][Coop<WAVES>::kSteps][kWave];
+    __shared__ float ring_b[2][Coop<WAVES>::kSteps][kWave];
     __shared__ uint32_t s_pop;
     const ExactLds* s_ex = (const ExactLds*)s_ex_raw;  // the top rows only (no learned variable here)
     for (int i = threadIdx.x; i < kTableRowsDev * (DEG + 1); i += blockDim.x) {
@@ -215,8 +223,8 @@ __global__ __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))
         const LevelParams& prm = params[ct.x];
         __builtin_amdgcn_s_setprio(3);
         const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-        if (variant[ct.x] & 1) run_chunk_coop<RV, true>(prm, ct.y, s_tab32, s_ex, ring_x, ring_b);
-        else run_chunk_coop<RV, false>(prm, ct.y, s_tab32, s_ex, ring_x, ring_b);
+        if (variant[ct.x] & 1) run_chunk_coop<RV, true, WAVES>(prm, ct.y, s_tab32, s_ex, ring_x, ring_b);
+        else run_chunk_coop<RV, false, WAVES>(prm, ct.y, s_tab32, s_ex, ring_x, ring_b);
         const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
         if (lane == 0) atomicAdd(&ticks[ct.x], (unsigned long long)(t1 - t0));
         __builtin_amdgcn_s_setprio(0);
@@ -275,13 +283,15 @@ __global__ __launch_bounds__(kReduceBlock) void batch_reduce_stage2(const uint64
     reduce_stage2(stage + row_off[item] * kPartial, rows[item], out + (uint64_t)item * kPartial, s);
 }
 
-constexpr mlmc_batch_cfg_t kDefaultCfg = {16, 1024, 12, 12};
+constexpr mlmc_batch_cfg_t kDefaultCfg = {16, 1024, 12, 12, kDefaultBlockWaves};
 
 int validate_cfg(const mlmc_batch_cfg_t& c) {
     if (c.waves_per_cu < 4 || c.waves_per_cu > 32) return set_error(MLMC_EINVAL, "waves_per_cu must be 4..32");
     if (c.task_steps < 1 || c.task_steps > (1 << 20)) return set_error(MLMC_EINVAL, "task_steps must be 1..2^20");
     if (c.priority_level < 0 || c.priority_level > 25) return set_error(MLMC_EINVAL, "priority_level must be 0..25");
     if (c.coop_level < 2 || c.coop_level > 25) return set_error(MLMC_EINVAL, "coop_level must be 2..25");
+    if (c.block_waves != 4 && c.block_waves != 8) return set_error(MLMC_EINVAL, "block_waves must be 4 or 8");
+    if (c.waves_per_cu < c.block_waves) return set_error(MLMC_EINVAL, "waves_per_cu is below one block");
     return MLMC_OK;
 }
 
@@ -292,6 +302,7 @@ mlmc_batch_cfg_t merged(const mlmc_batch_cfg_t* c) {
         if (c->task_steps) r.task_steps = c->task_steps;
         if (c->priority_level) r.priority_level = c->priority_level;
         if (c->coop_level) r.coop_level = c->coop_level;
+        if (c->block_waves) r.block_waves = c->block_waves;
     }
     return r;
 }
@@ -323,9 +334,9 @@ bool cache_lookup(const std::string& key, mlmc_batch_cfg_t* c) {
     while (std::getline(f, line)) {
         std::istringstream in(line);
         std::string k;
-        int a, s, p, q;
-        if ((in >> k >> a >> s >> p >> q) && k == key) {
-            *c = mlmc_batch_cfg_t{a, s, p, q};
+        int a, s, p, q, w;
+        if ((in >> k >> a >> s >> p >> q >> w) && k == key) {
+            *c = mlmc_batch_cfg_t{a, s, p, q, w};
             return validate_cfg(*c) == MLMC_OK;
         }
     }
@@ -344,7 +355,8 @@ void cache_store(const std::string& key, const mlmc_batch_cfg_t& c) {
     }
     std::ofstream f(path, std::ios::trunc);
     for (const std::string& l : keep) f << l << "\n";
-    f << key << " " << c.waves_per_cu << " " << c.task_steps << " " << c.priority_level << " " << c.coop_level << "\n";
+    f << key << " " << c.waves_per_cu << " " << c.task_steps << " " << c.priority_level << " " << c.coop_level << " "
+      << c.block_waves << "\n";
 }
 
 int hipck(hipError_t e, const char* what) {
@@ -386,21 +398,28 @@ std::vector<uint4> build_tasks(const mlmc_batch& b, const std::vector<uint64_t>&
     return out;
 }
 
+template <int RV, int WAVES>
+void launch_batch(const mlmc_batch* b, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((batch_kernel<RV, WAVES>), dim3(blocks), dim3(WAVES * kWave), 0, s, b->d_params, b->d_variant,
+                       b->d_tasks, (uint32_t)b->n_tasks, b->d_coop, (uint32_t)b->n_coop, b->d_counter,
+                       (const float*)b->tab32, (const __half*)b->tab16, b->exact_tab, b->d_ticks);
+}
+
 int enqueue(mlmc_batch* b, hipStream_t s) {
-    const int blocks = std::max(1, b->n_cu * b->cfg.waves_per_cu / (kBatchBlock / kWave));
+    const int bw = b->cfg.block_waves;
+    const int blocks = std::max(1, b->n_cu * b->cfg.waves_per_cu / bw);
     const uint32_t n_items = (uint32_t)b->items.size();
     hipLaunchKernelGGL(batch_reset, dim3(std::min<uint32_t>(64, (n_items + 255) / 256)), dim3(256), 0, s, b->d_counter,
                        b->d_ticks, n_items);
     int rc = hipck(hipGetLastError(), "queue reset launch");
     if (rc) return rc;
-    if (b->rv == MLMC_RV_CUBIC16)
-        hipLaunchKernelGGL(batch_kernel<MLMC_RV_CUBIC16>, dim3(blocks), dim3(kBatchBlock), 0, s, b->d_params,
-                           b->d_variant, b->d_tasks, (uint32_t)b->n_tasks, b->d_coop, (uint32_t)b->n_coop,
-                           b->d_counter, (const float*)b->tab32, (const __half*)b->tab16, b->exact_tab, b->d_ticks);
-    else
-        hipLaunchKernelGGL(batch_kernel<MLMC_RV_PWL16>, dim3(blocks), dim3(kBatchBlock), 0, s, b->d_params,
-                           b->d_variant, b->d_tasks, (uint32_t)b->n_tasks, b->d_coop, (uint32_t)b->n_coop,
-                           b->d_counter, (const float*)b->tab32, (const __half*)b->tab16, b->exact_tab, b->d_ticks);
+    if (b->rv == MLMC_RV_CUBIC16) {
+        if (bw == 4) launch_batch<MLMC_RV_CUBIC16, 4>(b, blocks, s);
+        else launch_batch<MLMC_RV_CUBIC16, 8>(b, blocks, s);
+    } else {
+        if (bw == 4) launch_batch<MLMC_RV_PWL16, 4>(b, blocks, s);
+        else launch_batch<MLMC_RV_PWL16, 8>(b, blocks, s);
+    }
     rc = hipck(hipGetLastError(), "batch kernel launch");
     if (rc) return rc;
     hipLaunchKernelGGL(batch_reduce_stage1, dim3(b->n_reduce_blocks), dim3(kReduceBlock), 0, s, b->d_partials,
@@ -638,35 +657,41 @@ int mlmc_batch_autotune(mlmc_batch_t* plan, int repeats, mlmc_batch_cfg_t* best)
         (void)hipEventDestroy(e0);
         return rc;
     }
-    // wavefronts per CU: multiples of the 8-wave block up to what the kernel's register use
-    // lets reside at once (a persistent wave that cannot start before the queue drains is idle)
-    int blocks_per_cu = 0;
-    if (plan->rv == MLMC_RV_CUBIC16)
-        rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, batch_kernel<MLMC_RV_CUBIC16>, kBatchBlock, 0),
-                   "occupancy query");
-    else
-        rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, batch_kernel<MLMC_RV_PWL16>, kBatchBlock, 0),
-                   "occupancy query");
-    if (rc) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return rc;
+    // block shapes (8 or 4 waves) and, for each, wavefronts per CU in whole blocks up to what
+    // the kernel's registers and LDS let reside at once (a persistent wave that cannot start
+    // before the queue drains is idle)
+    std::vector<std::pair<int, int>> shapes;  // (block waves, waves per CU)
+    for (int bw : {8, 4}) {
+        int blocks_per_cu = 0;
+        const void* fn = plan->rv == MLMC_RV_CUBIC16
+                             ? (bw == 8 ? (const void*)batch_kernel<MLMC_RV_CUBIC16, 8>
+                                        : (const void*)batch_kernel<MLMC_RV_CUBIC16, 4>)
+                             : (bw == 8 ? (const void*)batch_kernel<MLMC_RV_PWL16, 8>
+                                        : (const void*)batch_kernel<MLMC_RV_PWL16, 4>);
+        if ((rc = hipck(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, fn, bw * kWave, 0),
+                        "occupancy query"))) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return rc;
+        }
+        bool any = false;
+        for (int w = bw; w <= 32; w += bw)
+            if (w <= bw * blocks_per_cu) {
+                shapes.push_back({bw, w});
+                any = true;
+            }
+        if (!any) shapes.push_back({bw, bw});
     }
-    constexpr int kBlockWaves = kBatchBlock / kWave;
-    std::vector<int> waves;
-    for (int w = kBlockWaves; w <= 32; w += kBlockWaves)
-        if (w <= kBlockWaves * blocks_per_cu) waves.push_back(w);
-    if (waves.empty()) waves.push_back(kBlockWaves * std::max(1, blocks_per_cu));
     const int steps[] = {64, 256, 1024};
     const int prios[] = {12, 25};
     const int coops[] = {11, 12, 13, 25};
     mlmc_batch_cfg_t winner = plan->cfg;
     float best_ms = 1e30f;
-    for (int w : waves)
+    for (const auto& shape : shapes)
         for (int st : steps)
             for (int pr : prios)
                 for (int co : coops) {
-                plan->cfg = mlmc_batch_cfg_t{w, st, pr, co};
+                plan->cfg = mlmc_batch_cfg_t{shape.second, st, pr, co, shape.first};
                 if ((rc = prepare(plan))) goto done;
                 if ((rc = hipck(hipGraphLaunch(plan->exec, plan->cap_stream), "warm-up replay"))) goto done;
                 if ((rc = hipck(hipEventRecord(e0, plan->cap_stream), "hipEventRecord"))) goto done;

@@ -61,7 +61,8 @@ class mlmc_item_t(ctypes.Structure):
 
 class mlmc_batch_cfg_t(ctypes.Structure):
     _fields_ = [("waves_per_cu", ctypes.c_int32), ("task_steps", ctypes.c_int32),
-                ("priority_level", ctypes.c_int32), ("coop_level", ctypes.c_int32)]
+                ("priority_level", ctypes.c_int32), ("coop_level", ctypes.c_int32),
+                ("block_waves", ctypes.c_int32)]
 
 
 class mlmc_mlp_cfg_t(ctypes.Structure):

@@ -146,7 +146,8 @@ def test_batch_validation_before_device():
         M.mlmc_batch_create([M.item(s, 3, 10, M.MLMC_FP32)], M.MLMC_RV_EXACT, 1)
     assert e.value.code == M.MLMC_EINVAL
     for cfg in (M.mlmc_batch_cfg_t(16, 256, 25, 1), M.mlmc_batch_cfg_t(16, 256, 25, 26),
-                M.mlmc_batch_cfg_t(3, 256, 25, 13), M.mlmc_batch_cfg_t(16, 256, 26, 13)):
+                M.mlmc_batch_cfg_t(3, 256, 25, 13), M.mlmc_batch_cfg_t(16, 256, 26, 13),
+                M.mlmc_batch_cfg_t(16, 256, 25, 13, 6), M.mlmc_batch_cfg_t(4, 256, 25, 13, 8)):
         with pytest.raises(M.MlmcError) as e:
             M.mlmc_batch_create([M.item(s, 3, 10, M.MLMC_FP32)], M.MLMC_RV_PWL16, 1, cfg)
         assert e.value.code == M.MLMC_EINVAL

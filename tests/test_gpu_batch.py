@@ -63,23 +63,25 @@ def test_batch_items_equal_single_level_calls(rv):
         M.mlmc_batch_destroy(plan)
 
 
+@pytest.mark.parametrize("block_waves", [8, 4])
 @pytest.mark.parametrize("kahan32", [0, 1])
 @pytest.mark.parametrize("coop_level", [2, 7])
-def test_cooperative_chunks_equal_single_level_calls(coop_level, kahan32):
+def test_cooperative_chunks_equal_single_level_calls(coop_level, kahan32, block_waves):
     # binary32 items from level 2 (one Philox call: a partial first phase) to 12 (1024 calls:
-    # 342 phases, the last one partial), path counts not multiples of the chunk
+    # 342 phases of seven producers, 114 of three, the last one partial), path counts not
+    # multiples of the chunk; blocks of eight and of four waves
     torch = torch_cuda()
     psets = W.batch_parameter_sets(2, seed=9)
     items, meta = make_items(psets, range(13), lambda l: max(70, 9000 >> l) + 5, split=1, kahan32=kahan32)
     out = torch.zeros((len(items), 8), dtype=torch.float64, device="cuda")
-    cfg = M.mlmc_batch_cfg_t(16, 256, 25, coop_level)
+    cfg = M.mlmc_batch_cfg_t(16, 256, 25, coop_level, block_waves)
     plan = M.mlmc_batch_create(items, M.MLMC_RV_PWL16, out, cfg)
     try:
         M.mlmc_batch_run(plan)
         torch.cuda.synchronize()
         got = out.cpu().numpy()
         info, _ = M.mlmc_batch_info(plan)
-        assert info.coop_level == coop_level
+        assert info.coop_level == coop_level and info.block_waves == block_waves
         for i, it in enumerate(items):
             np.testing.assert_array_equal(got[i], single_level(it, M.MLMC_RV_PWL16), err_msg=str(meta[i][:4]))
     finally:
@@ -143,8 +145,9 @@ def test_autotune_keeps_results_and_returns_valid_shape(tmp_path, monkeypatch):
         best = M.mlmc_batch_autotune(plan, 1)
         assert 4 <= best.waves_per_cu <= 32 and best.task_steps >= 1
         cfg, n_tasks = M.mlmc_batch_info(plan)
-        assert (cfg.waves_per_cu, cfg.task_steps, cfg.priority_level, cfg.coop_level) == (
-            best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level)
+        assert (cfg.waves_per_cu, cfg.task_steps, cfg.priority_level, cfg.coop_level, cfg.block_waves) == (
+            best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level, best.block_waves)
+        assert best.block_waves in (4, 8) and best.waves_per_cu % best.block_waves == 0
         assert n_tasks > 0
         out.zero_()
         M.mlmc_batch_run(plan)
@@ -157,8 +160,8 @@ def test_autotune_keeps_results_and_returns_valid_shape(tmp_path, monkeypatch):
     plan2 = M.mlmc_batch_create(items, M.MLMC_RV_PWL16, out)
     try:
         cfg2, _ = M.mlmc_batch_info(plan2)
-        assert (cfg2.waves_per_cu, cfg2.task_steps, cfg2.priority_level, cfg2.coop_level) == (
-            best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level)
+        assert (cfg2.waves_per_cu, cfg2.task_steps, cfg2.priority_level, cfg2.coop_level, cfg2.block_waves) == (
+            best.waves_per_cu, best.task_steps, best.priority_level, best.coop_level, best.block_waves)
     finally:
         M.mlmc_batch_destroy(plan2)
 
