@@ -10,7 +10,8 @@ with on-device binary64 sums and sums of squares.
 
 Metric: coupled path-steps per second (one coupled path-step = one fine time step of one
 coupled sample, including its share of the coarse step) -- inputs are seeds, resident on
-the device by construction.  Besides the headline number the JSON line reports the plain
+the device by construction.  A step is one pass of the 22 level calls, captured once as a
+hipGraph and replayed (every replay's sums are checked equal to the eager pass's).  Besides the headline number the JSON line reports the plain
 binary64 estimator's throughput at the same sizes and the speed-up of the nested
 binary32 estimator over it at equal total MLMC variance (T^ / T-, from measured
 per-level variances and device costs), the roofline of the dominant kernel and the CPU
@@ -157,34 +158,47 @@ def main():
     ws_bytes = max(M.mlmc_level_workspace_bytes(x) for x in args[0])
     ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device="cuda")
     top = LEVELS[-1]
-    ev = []   # (start, end) events around the dominant call: level 10, Kahan (kernel + reduction)
 
-    def step(record):
+    def step(st):
         for k in (0, 1):
             for i, l in enumerate(LEVELS):
-                timed = record and k == 1 and l == top
-                if timed:
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                M.mlmc_level_ex(args[k][i], out[k, i], ws, ws_bytes, stream)
-                if timed:
-                    e1.record(stream)
-                    ev.append((e0, e1))
+                M.mlmc_level_ex(args[k][i], out[k, i], ws, ws_bytes, st)
 
+    # one pass (22 level calls, each its level kernel and two reduction kernels) captured once
+    # as a hipGraph and replayed: the GPU work of a step without per-launch host overhead
+    for _ in range(max(1, a.warmup)):
+        step(stream)
+    torch.cuda.synchronize()
+    eager = out.cpu().numpy().copy()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step(torch.cuda.current_stream())
+    torch.cuda.synchronize()
     for _ in range(a.warmup):
-        step(False)
+        graph.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        step(True)
+        graph.replay()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     steps_per_pass = 2 * N_PATHS * sum(2 ** l for l in LEVELS)
     seconds = t1 - t0
     value = a.steps * steps_per_pass / seconds
-    launch_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
     sums = out.cpu().numpy()
     assert all(math.isfinite(v) for v in sums.ravel()), "non-finite level sums"
+    # every replay computes the same samples as the eager pass, bit for bit
+    assert (sums == eager).all(), "graph replay differs from the eager pass"
+    # the dominant call alone, eagerly: level 10 with Kahan updates, kernel plus reduction
+    ev = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        M.mlmc_level_ex(args[1][top], out[1, top], ws, ws_bytes, stream)
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    launch_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
 
     roof = {k: roofline_block(M, torch, k) for k in ROOFLINE_KERNELS}
     roof["fp32"]["call_ms_with_reduction"] = launch_ms
@@ -225,7 +239,7 @@ def main():
         "config": {"workload": "nested four-way MLMC, GBM mu=0.05 sigma=0.2 X0=1 T=1, call K=1, "
                                "binary32 approximate pair with piecewise-linear inverse CDF on 16 dyadic "
                                "intervals, binary64 exact pair, levels 0..10, 2^20 paths/level, "
-                               "Kahan off and on",
+                               "Kahan off and on; one pass of the 22 level calls replayed as a hipGraph",
                    "levels": LEVELS, "paths_per_level": N_PATHS, "kahan": [0, 1],
                    "coupled_path_steps_per_step": steps_per_pass, "parallelism": "single GPU"},
         "roofline": roof["fp32"],
