@@ -137,6 +137,24 @@ def test_nested_mlp_paths_match_oracle(level):
     assert np.all(close(g["pf_bar"][exact], o["Pf_bar"][exact], 1e-5))
 
 
+def test_full_size_sampled_mlp_paths_level10():
+    """The learned variable's workload at full size: 2^22 paths at level 10 in the benchmark's
+    launch, sampled paths against the oracle (binary32 bar plus the rounding allowance)."""
+    torch = torch_cuda()
+    p = W.mlp_initial_params(5) + np.random.default_rng(6).normal(0, 0.1, mlp.N_PARAMS)
+    M.mlmc_mlp_load(dev(p))
+    q = mlp.deployed(p.astype(np.float32))
+    n, level = W.MLP_PATHS, 10
+    g = gpu_paths(W.GBM_CALL, level, n, M.MLMC_FP32, M.MLMC_RV_MLP, True, 0, 0)
+    idx = W.sampled_paths(n, 24)
+    o = mlmc.level_paths(level, idx, W.GBM_CALL, rv_mode=mlmc.RV_MLP, precision=fp.FP32, nested=True,
+                         kahan=False, seed=0, stream=1, mlp_params=q)
+    assert np.max(np.abs(g["pf_hat"][idx] - o["Pf_hat"])) <= 1e-13 * max(1.0, np.max(np.abs(o["Pf_hat"])))
+    for key, ref in (("pf_bar", "Pf_bar"), ("pc_bar", "Pc_bar")):
+        err = np.abs(g[key][idx] - o[ref])
+        assert np.all(err <= 1e-5 * np.maximum(np.abs(o[ref]), 1.0) + o[ref + "_allow"]), key
+
+
 @pytest.fixture(scope="module")
 def trained():
     torch = torch_cuda()

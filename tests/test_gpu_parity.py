@@ -231,6 +231,22 @@ def test_full_size_sampled_paths_fp16():
     assert np.all(close(g["pf_hat"][idx], o["Pf_hat"], 1e-13))
 
 
+@pytest.mark.parametrize("level", [0, 1])
+def test_full_size_sampled_paths_coarse_levels(level):
+    """The benchmark's coarse levels at full size (shared Philox calls): binary32 nested at 2^20
+    paths and packed binary16 nested at 2^24, sampled paths (the ends of the range included)."""
+    for precision, rv, n in ((M.MLMC_FP32, mlmc.RV_PWL, W.NESTED_FP32["n_paths"]),
+                             (M.MLMC_FP16, mlmc.RV_CUBIC, W.NESTED_FP16["n_paths"])):
+        sde = W.NESTED_FP32["sde"]
+        g = gpu_paths(sde, level, n, precision, rv, True, 1, 0)
+        idx = W.sampled_paths(n, 48)
+        o = mlmc.level_paths(level, idx, sde, rv_mode=rv, precision=fp.FP32 if precision == M.MLMC_FP32 else fp.FP16,
+                             nested=True, kahan=True, seed=0, stream=1)
+        assert np.all(close(g["pf_hat"][idx], o["Pf_hat"], 1e-13))
+        np.testing.assert_array_equal(g["pf_bar"][idx], o["Pf_bar"])
+        np.testing.assert_array_equal(g["pc_bar"][idx], o["Pc_bar"])
+
+
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 129])
 def test_edge_path_counts(n):
     r = M.mlmc_level(M.gbm(), 2, n, M.MLMC_FP32, M.MLMC_NESTED_CUBIC16, 1, 5)
