@@ -67,7 +67,7 @@ ROOFLINE_KERNELS = {
                  kernel="level_kernel<FP16, CUBIC16, nested, Kahan> at level 6 (2^24 paths x 64 steps)"),
 }
 # the sources and build flags the counts above were taken from (sha256 of ISA_SOURCES)
-ISA_SOURCES_SHA256 = "614cb7327aba0e93e0c1e037ab8117ce200241fd05b29661fda74e5d2789399a"
+ISA_SOURCES_SHA256 = "bc197b214aeccc357d0c5cc62cdc9ef266fa066038dde8de02f8a4a9b1878a7e"
 # HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB;
 # scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
 TRAFFIC_BYTES_PER_LAUNCH = {"fp32": (218.938 * 2.0 + 1024.0) * 1024, "fp16": (3311.94 * 2.0 + 14336.0) * 1024}
@@ -648,14 +648,15 @@ def reports(M, E, torch, legs=REPORT_LEGS):
     if "marginal" in legs:
         # marginal device cost per coupled path-step of the level kernel alone, (t(4n) - t(n)) /
         # (3 n 2^l), at the coarse levels (where the MLMC allocation puts most samples) and at
-        # level 10, from HIP events around mlmc_paths
+        # level 10, from HIP events around mlmc_paths; n = 2^24 / 2^l paths (2^18 at level 10), so
+        # that both launches hold several times the resident waves
         marg = {}
         for tag, prec, mode, k in (("nested_fp32_pwl16_kahan", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1),
                                    ("nested_fp16_cubic16_kahan", M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1),
                                    ("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0)):
             row = {}
             for l in (0, 1, 2, 3, 10):
-                n = 2 ** 20 if l < 10 else 2 ** 18
+                n = 2 ** 24 >> l if l < 10 else 2 ** 18
                 t1 = sum(kernel_ms(M, torch, M.level_args(call, l, n, prec, mode, k, SEED))) / 10
                 t4 = sum(kernel_ms(M, torch, M.level_args(call, l, 4 * n, prec, mode, k, SEED))) / 10
                 row["level_%d" % l] = {"ms_n": t1, "ms_4n": t4, "n": n,

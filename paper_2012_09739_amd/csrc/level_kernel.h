@@ -126,31 +126,65 @@ __device__ __forceinline__ __half payoff_h(__half X, __half K, int kind) {
 // ---- fixed-order wave reduction of the 8 partial values ------------------------------
 // Lane i and lane i ^ 32 swap half of their eight values and each adds the half it keeps
 // (lanes with bit 5 clear keep values 0..3, the others 4..7); then i ^ 16 halves again and
-// i ^ 8 leaves one value per lane; a butterfly over the lowest three lane bits completes it.
-// Lane 8k ends with the total of value k.  The order of every addition depends on the lane
-// numbers only, so the result is reproducible; 10 exchanges of a double instead of the 48 of
-// eight separate butterflies.
+// i ^ 8 leaves one value per lane; three exchanges inside each group of eight lanes (its
+// mirror image, then i ^ 2, then i ^ 1) complete the sums.  Lane 8k ends with the total of
+// value k.  The order of every addition depends on the lane numbers only, so the result is
+// reproducible.  The exchanges stay in the VALU: the half-wave and row swaps of gfx950
+// (v_permlane32_swap, v_permlane16_swap) for the first two, row-local DPP moves for the rest,
+// each on the two 32-bit halves of a double.
+__device__ __forceinline__ uint32_t lo32(double x) { return (uint32_t)__builtin_bit_cast(uint64_t, x); }
+__device__ __forceinline__ uint32_t hi32(double x) { return (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32); }
+__device__ __forceinline__ double join64(uint32_t lo, uint32_t hi) {
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// a's lanes 32..63 trade places with b's lanes 0..31: a lane of the lower half then holds its
+// own a and the upper partner's a, a lane of the upper half the lower partner's b and its own b
+__device__ __forceinline__ void swap_half_waves(double& a, double& b) {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+    a = join64(l[0], h[0]);
+    b = join64(l[1], h[1]);
+}
+// the same between the odd rows (16 lanes) of a and the even rows of b
+__device__ __forceinline__ void swap_rows(double& a, double& b) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+    a = join64(l[0], h[0]);
+    b = join64(l[1], h[1]);
+}
+// the value of the lane that DPP control CTRL names (inside the lane's row)
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+    return join64((uint32_t)__builtin_amdgcn_mov_dpp((int)lo32(x), CTRL, 0xf, 0xf, false),
+                  (uint32_t)__builtin_amdgcn_mov_dpp((int)hi32(x), CTRL, 0xf, 0xf, false));
+}
+constexpr int kDppRowRor8 = 0x128;       // lane i of a row reads lane (i + 8) mod 16 = i ^ 8
+constexpr int kDppHalfMirror = 0x141;    // lane i of a group of eight reads lane 7 - i
+constexpr int kDppQuadXor2 = 0x4e;       // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuadXor1 = 0xb1;       // quad_perm [1, 0, 3, 2]
+
+// Every lane of the wave takes part (called with the full execution mask).
 __device__ __forceinline__ void store_row(const double (&acc)[kPartial], uint32_t lane, double* out) {
     static_assert(kPartial == 8, "three halving exchanges");
-    const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0, h3 = (lane & 8) != 0;
     double v4[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const double send = h5 ? acc[j] : acc[4 + j];
-        const double keep = h5 ? acc[4 + j] : acc[j];
-        v4[j] = keep + __shfl_xor(send, 32, kWave);
+        double a = acc[j], b = acc[4 + j];
+        swap_half_waves(a, b);
+        v4[j] = a + b;  // value j in the lower half-wave, 4 + j in the upper
     }
     double v2[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const double send = h4 ? v4[j] : v4[2 + j];
-        const double keep = h4 ? v4[2 + j] : v4[j];
-        v2[j] = keep + __shfl_xor(send, 16, kWave);
+        double a = v4[j], b = v4[2 + j];
+        swap_rows(a, b);
+        v2[j] = a + b;  // even rows keep the first two of their four values, odd rows the last two
     }
-    double v = (h3 ? v2[1] : v2[0]) + __shfl_xor(h3 ? v2[0] : v2[1], 8, kWave);
-    v += __shfl_xor(v, 4, kWave);
-    v += __shfl_xor(v, 2, kWave);
-    v += __shfl_xor(v, 1, kWave);
+    const bool h3 = (lane & 8) != 0;
+    double v = (h3 ? v2[1] : v2[0]) + dpp64<kDppRowRor8>(h3 ? v2[0] : v2[1]);
+    v += dpp64<kDppHalfMirror>(v);
+    v += dpp64<kDppQuadXor2>(v);
+    v += dpp64<kDppQuadXor1>(v);
     if ((lane & 7) == 0) out[lane >> 3] = v;
 }
 
@@ -190,8 +224,10 @@ __device__ __forceinline__ T approx_rv(uint32_t w, const T* tab, const float* ml
 // coefficient table in the working precision (binary32: prescaled, see prescaled_coeff) and
 // s_tab64 the binary64 one (diagnostic), both in LDS.  SHORT (levels 0 and 1): the caller
 // draws the words, whose calls several paths share, and names each lane's paths in
-// sh_words / sh_local (chunk is then unused).
-template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM>
+// sh_words / sh_local (chunk is then unused); NS is then the level's fine step count (1 or 2),
+// known at compile time so that the step loop and the payoffs unroll without tests.
+template <int PREC, int RV, bool NESTED, bool KAHAN, bool DIAG, bool SHORT = false, int SCHEME = MLMC_SCHEME_EM,
+          int NS = 0>
 __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chunk, uint32_t lane, const void* s_tab_v,
                                             const double* s_tab64, const ExactLds* s_ex, double (&acc)[kPartial],
                                             const Words4* sh_words = nullptr, const uint64_t* sh_local = nullptr) {
@@ -208,7 +244,8 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
     const __half* s_tab16 = (const __half*)s_tab_v;
     const float* mlpw = (const float*)s_tab_v;  // the MLP image when RV is MLMC_RV_MLP
     constexpr uint32_t kChunk = kWave * L;
-    const uint32_t n_calls = (prm.n_steps + 3) / 4;
+    static_assert(SHORT == (NS == 1 || NS == 2) && (SHORT || NS == 0), "SHORT instances know their step count");
+    const uint32_t n_calls = SHORT ? 1u : (prm.n_steps + 3) / 4;
 
     uint64_t local[L];
     bool valid[L];
@@ -274,7 +311,7 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
                     zx[l][0] = icdf_exact_f64(r[l].w[0], &s_ex->top, deep_rows(prm));
-                    zx[l][1] = prm.n_steps > 1 ? icdf_exact_f64(r[l].w[1], &s_ex->top, deep_rows(prm)) : 0.0;
+                    if constexpr (NS > 1) zx[l][1] = icdf_exact_f64(r[l].w[1], &s_ex->top, deep_rows(prm));
                 }
             }
         }
@@ -291,7 +328,7 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
         for (int i = 0; i < 4; ++i) {
             // only levels 0 and 1 stop inside a call, and they run as SHORT instances
             if constexpr (SHORT)
-                if (4 * q + i >= prm.n_steps) break;
+                if (i >= NS) break;
             const bool coarse = (i & 1) != 0;
             if constexpr (kNeedExact && SHORT) {
 #pragma unroll
@@ -349,7 +386,7 @@ __device__ __forceinline__ void chunk_terms(const LevelParams& prm, uint64_t chu
     }
 
     // payoffs and differences (binary64), then the lane's contribution to the sums
-    const bool has_coarse = prm.level >= 1;
+    const bool has_coarse = SHORT ? NS > 1 : prm.level >= 1;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         double t[kTerms] = {0.0, 0.0, 0.0, 0.0};
@@ -451,7 +488,8 @@ __device__ __forceinline__ void short_row_terms(const LevelParams& prm, uint64_t
                     }
                 }
             }
-            chunk_terms<PREC, RV, NESTED, KAHAN, DIAG, true, SCHEME>(prm, 0, lane, s_tab_v, s_tab64, s_ex, acc, w, loc);
+            chunk_terms<PREC, RV, NESTED, KAHAN, DIAG, true, SCHEME, S>(prm, 0, lane, s_tab_v, s_tab64, s_ex, acc, w,
+                                                                       loc);
         }
     }
 }
