@@ -70,8 +70,8 @@ ROOFLINE_KERNELS = {
 ISA_SOURCES_SHA256 = "bc197b214aeccc357d0c5cc62cdc9ef266fa066038dde8de02f8a4a9b1878a7e"
 # HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB;
 # scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
-TRAFFIC_BYTES_PER_LAUNCH = {"fp32": (218.938 * 2.0 + 1024.0) * 1024, "fp16": (3311.94 * 2.0 + 14336.0) * 1024}
-TRAFFIC_SOURCES_SHA256 = "e5cdd2cf5be2e8817b832c36394ad97112bb951bfbcab2d1cc001d2d5df49382"
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": (218.438 * 2.0 + 1024.0) * 1024, "fp16": (243.938 * 2.0 + 8192.0) * 1024}
+TRAFFIC_SOURCES_SHA256 = "0555ba34db0993c66ba89345e0285816b50b6bc0bd86590f214522e9b2b216b1"
 # what a kernel's instructions depend on: its sources and the build flags
 ISA_SOURCES = ("csrc/level_kernel.h", "csrc/level_launch.h", "csrc/icdf.h", "csrc/philox.h", "csrc/mlp.h",
                "csrc/internal.h", "csrc/level_f32.hip", "csrc/level_f16.hip", "csrc/icdf_exact_coeffs.h", "build.py")
