@@ -67,11 +67,11 @@ ROOFLINE_KERNELS = {
                  kernel="level_kernel<FP16, CUBIC16, nested, Kahan> at level 6 (2^24 paths x 64 steps)"),
 }
 # the sources and build flags the counts above were taken from (sha256 of ISA_SOURCES)
-ISA_SOURCES_SHA256 = "bc197b214aeccc357d0c5cc62cdc9ef266fa066038dde8de02f8a4a9b1878a7e"
+ISA_SOURCES_SHA256 = "fb91e4feea312f5287ba98d46dd3ebfcb2f49d58824fb3b188d688d1f4bbf9ea"
 # HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB;
 # scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
 TRAFFIC_BYTES_PER_LAUNCH = {"fp32": (218.438 * 2.0 + 1024.0) * 1024, "fp16": (243.938 * 2.0 + 8192.0) * 1024}
-TRAFFIC_SOURCES_SHA256 = "0555ba34db0993c66ba89345e0285816b50b6bc0bd86590f214522e9b2b216b1"
+TRAFFIC_SOURCES_SHA256 = "08b64192159d5608561579fef455a304b166e4769f62782fa82c22318462149e"
 # what a kernel's instructions depend on: its sources and the build flags
 ISA_SOURCES = ("csrc/level_kernel.h", "csrc/level_launch.h", "csrc/icdf.h", "csrc/philox.h", "csrc/mlp.h",
                "csrc/internal.h", "csrc/level_f32.hip", "csrc/level_f16.hip", "csrc/icdf_exact_coeffs.h", "build.py")
@@ -259,6 +259,7 @@ def equal_variance_summary(extra):
     for tag, key in (("fp32_pwl16_levels0to10", "fp32"), ("fp32_pwl16_kahan_levels0to10", "fp32_kahan")):
         if key in ev:
             out[tag] = ev[key]["speedup_T_hat_over_T_bar"]
+            out[tag + "_marginal_costs"] = ev[key]["speedup_T_hat_over_T_bar_marginal_costs"]
     rep = extra.get("reports", {})
     f16 = rep.get("nested_fp16_cubic16_kahan_levels0to6_2p24")
     if f16:
@@ -359,7 +360,9 @@ def equal_variance_report(M, E, call):
     v^_l, c^_l: two-way exact differences in binary64 (the plain estimator's samples);
     v-_l, c-_l: approximate two-way differences in binary32 (independent Philox stream 0);
     V-_l, C-_l: four-way differences (nested samples, stream 1); costs are device times
-    per sample from the library's HIP events."""
+    per sample from the library's HIP events: of the 2^20-path calls (fixed cost of a call
+    included), and marginal (without it, the regime of small tolerances, where the coarse
+    levels take many more samples)."""
     rep = {}
     res = {}
     for name, prec, mode, k in (("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0),
@@ -376,6 +379,14 @@ def equal_variance_report(M, E, call):
         res[name] = rows
     cost = lambda rows: [r["cost_seconds"] / r["n_paths"] for r in rows]  # noqa: E731
     var = lambda rows, t: [E.level_stats(r["sum"][t], r["sumsq"][t], r["n_paths"])[1] for r in rows]  # noqa: E731
+    # per-sample costs without the fixed cost of a call (launch, reduction): what a sample costs
+    # when the optimal allocation asks for many more than 2^20 at the coarse levels
+    marg = {name: _marginal_costs(M, M.gbm(payoff=M.MLMC_PAYOFF_CALL), LEVELS, prec, mode, k)
+            for name, prec, mode, k in (("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0),
+                                        ("approx_fp32", M.MLMC_FP32, M.MLMC_APPROX_PWL16, 0),
+                                        ("approx_fp32_kahan", M.MLMC_FP32, M.MLMC_APPROX_PWL16, 1),
+                                        ("nested_fp32", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0),
+                                        ("nested_fp32_kahan", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1))}
     v_hat, c_hat = var(res["plain_fp64"], 0), cost(res["plain_fp64"])
     steps = N_PATHS * sum(2 ** l for l in LEVELS)
     rep["fp64_plain_path_steps_per_s"] = steps / sum(r["cost_seconds"] for r in res["plain_fp64"])
@@ -386,11 +397,30 @@ def equal_variance_report(M, E, call):
         V_bar, C_bar = var(res[ne], 1), cost(res[ne])
         rep["equal_variance"][tag] = {
             "speedup_T_hat_over_T_bar": E.speedup_equal_variance(v_hat, c_hat, v_bar, c_bar, V_bar, C_bar),
+            "speedup_T_hat_over_T_bar_marginal_costs": E.speedup_equal_variance(
+                v_hat, marg["plain_fp64"], v_bar, marg[ap], V_bar, marg[ne]),
+            "marginal_cost_per_sample_s": {"plain_fp64": marg["plain_fp64"], "approx": marg[ap], "nested": marg[ne]},
             "per_level_speedup": [1.0 / f for f in E.per_level_factor(v_hat, c_hat, v_bar, c_bar, V_bar, C_bar)],
             "approx_two_way_path_steps_per_s": steps / sum(r["cost_seconds"] for r in res[ap]),
             "four_way_over_two_way_variance": [V / v for V, v in zip(V_bar, v_hat)],
         }
     return rep
+
+
+def _marginal_costs(M, sde, levels, prec, mode, kahan, seed=SEED, reps=3):
+    """Per-sample device cost without the call's fixed part: (c(4n) - c(n)) / (3n) from the
+    library's HIP events (median of `reps` calls each), n = max(2^20, 2^24 / 2^l) so that both
+    calls hold several times the resident waves."""
+    out = []
+    for l in levels:
+        n = max(N_PATHS, 2 ** 24 >> l)
+        t = []
+        for m in (n, 4 * n):
+            M.mlmc_level(sde, l, m, prec, mode, kahan, seed)
+            c = sorted(M.mlmc_level(sde, l, m, prec, mode, kahan, seed)["cost_seconds"] for _ in range(reps))
+            t.append(c[reps // 2])
+        out.append((t[1] - t[0]) / (3 * n))
+    return out
 
 
 def _level_costs(M, sde, levels, n, prec, mode, kahan, seed=SEED):

@@ -363,7 +363,11 @@ uint64_t n_chunks_of(const mlmc_level_args_t* a) {
     return (a->n_paths + cp - 1) / cp;
 }
 
-uint64_t n_rows_of(const mlmc_level_args_t* a) { return rows_of(n_chunks_of(a), a->level); }
+// approximate-only estimators (no exact variable): their rows group more chunks from level 2
+bool approx_only_mode(int rv_mode) { return rv_mode != MLMC_EXACT && rv_mode < MLMC_NESTED_PWL16; }
+uint64_t n_rows_of(const mlmc_level_args_t* a) {
+    return rows_of(n_chunks_of(a), a->level, approx_only_mode(a->rv_mode));
+}
 
 LevelParams make_params(const mlmc_level_args_t* a, const Variant& v, const DevState& st, double* partials) {
     LevelParams p;

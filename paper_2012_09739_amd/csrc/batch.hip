@@ -379,7 +379,7 @@ std::vector<uint4> build_tasks(const mlmc_batch& b, const std::vector<uint64_t>&
             continue;
         }
         // rows of row_chunks(l) chunks: about task_steps steps per path and task
-        const uint64_t g = row_chunks(l);
+        const uint64_t g = row_chunks(l, false);  // nested items
         const uint64_t per = std::max<uint64_t>(1, ((uint64_t)b.cfg.task_steps >> l) / g);
         const uint32_t prio = l >= b.cfg.priority_level ? 1u : 0u;
         for (uint64_t c = 0; c < rows[i]; c += per) {
@@ -443,7 +443,7 @@ int prepare(mlmc_batch* b) {
     std::vector<uint64_t> rows(b->items.size());
     for (size_t i = 0; i < b->items.size(); ++i) {
         const uint64_t cp = chunk_paths(b->items[i].precision);
-        rows[i] = rows_of((b->items[i].n_paths + cp - 1) / cp, b->items[i].level);
+        rows[i] = rows_of((b->items[i].n_paths + cp - 1) / cp, b->items[i].level, false);
     }
     std::vector<uint2> coop;
     const std::vector<uint4> tasks = build_tasks(*b, rows, &coop);
@@ -531,7 +531,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
         if (it.stream > 0xFFFFu) return set_error(MLMC_EINVAL, "item %d: stream exceeds 65535", i);
         if (it.n_paths == 0 || it.n_paths > (1ull << 32))
             return set_error(MLMC_EINVAL, "item %d: n_paths must be 1..2^32", i);
-        total_rows += rows_of((it.n_paths + chunk_paths(it.precision) - 1) / chunk_paths(it.precision), it.level);
+        total_rows += rows_of((it.n_paths + chunk_paths(it.precision) - 1) / chunk_paths(it.precision), it.level, false);
     }
     const mlmc_batch_cfg_t c0 = merged(cfg);
     int rc = validate_cfg(c0);
@@ -561,7 +561,7 @@ int mlmc_batch_create(const mlmc_item_t* items, int n_items, int rv, const mlmc_
     uint64_t acc = 0;
     for (int i = 0; i < n_items; ++i) {
         const mlmc_item_t& it = items[i];
-        rows[i] = rows_of((it.n_paths + chunk_paths(it.precision) - 1) / chunk_paths(it.precision), it.level);
+        rows[i] = rows_of((it.n_paths + chunk_paths(it.precision) - 1) / chunk_paths(it.precision), it.level, false);
         off[i] = acc;
         acc += rows[i];
         var[i] = variant_of(it.precision, it.kahan);

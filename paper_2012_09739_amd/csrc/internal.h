@@ -69,11 +69,17 @@ hipError_t launch_reduce(const double* partials, uint64_t n_rows, double* stage,
 // Chunks per partial row.  A row is the unit of the fixed-order reduction: a wave simulates
 // the row's chunks one after another, each lane adding its paths' terms in that order, then
 // reduces the row once.  At the coarse levels a chunk is only a few steps long, so the wave
-// reduction and the per-wave set-up would otherwise cost more than the paths; grouping depends
-// on the level alone, so every call and batch item of a level reduces its paths alike.
-__host__ __device__ constexpr inline uint32_t row_chunks(int level) { return level >= 2 ? 1u : (8u >> level); }
-__host__ __device__ inline uint64_t rows_of(uint64_t n_chunks, int level) {
-    const uint64_t g = row_chunks(level);
+// reduction and the per-wave set-up would otherwise cost more than the paths.  Levels 0 and 1
+// take 8 and 4 chunks per row; from level 2 the instances with the exact variable take one
+// (their sums then hold no registers during the steps), the approximate-only ones 8, 4 and 2
+// at levels 2, 3 and 4 (at least 32 steps per lane between two reductions) and one above.
+// Grouping depends on the level and the estimator's kind alone, so every call and batch item
+// of a level and kind reduces its paths alike.
+__host__ __device__ constexpr inline uint32_t row_chunks(int level, bool approx_only) {
+    return level < 2 ? (8u >> level) : (approx_only && level < 5) ? (32u >> level) : 1u;
+}
+__host__ __device__ inline uint64_t rows_of(uint64_t n_chunks, int level, bool approx_only) {
+    const uint64_t g = row_chunks(level, approx_only);
     return (n_chunks + g - 1) / g;
 }
 

@@ -456,7 +456,7 @@ __device__ __forceinline__ void short_row_terms(const LevelParams& prm, uint64_t
                                                 const double* s_tab64, const ExactLds* s_ex, double (&acc)[kPartial]) {
     constexpr uint32_t S = 1u << LEVEL, G = 4u >> LEVEL;
     constexpr uint32_t L = (PREC == MLMC_FP16) ? 2 : 1;
-    constexpr uint32_t kRowPaths = row_chunks(LEVEL) * kWave * L;
+    constexpr uint32_t kRowPaths = row_chunks(LEVEL, false) * kWave * L;
     static_assert(kRowPaths % (kWave * G) == 0 && G % L == 0, "whole groups per lane");
     const uint64_t first = row * kRowPaths;
     const uint32_t shift = (uint32_t)(prm.path_offset % G);  // wave-uniform
@@ -509,7 +509,7 @@ __device__ __forceinline__ void run_row(const LevelParams& prm, uint64_t row, ui
     } else {
         constexpr uint32_t kChunk = kWave * ((PREC == MLMC_FP16) ? 2 : 1);
         const uint64_t n_chunks = (prm.n_paths + kChunk - 1) / kChunk;
-        const uint64_t g = row_chunks(prm.level);
+        const uint64_t g = row_chunks(prm.level, true);  // approximate-only instances
         const uint64_t c0 = row * g;
         const uint64_t c1 = c0 + g < n_chunks ? c0 + g : n_chunks;
         for (uint64_t c = c0; c < c1; ++c)
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHORT ? 1 :
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) / kWave;
     constexpr uint32_t kChunk = kWave * L;
-    const uint64_t n_rows = rows_of((prm.n_paths + kChunk - 1) / kChunk, prm.level);
+    const uint64_t n_rows = rows_of((prm.n_paths + kChunk - 1) / kChunk, prm.level, !NESTED && RV != MLMC_RV_EXACT);
     for (uint64_t row = wave; row < n_rows; row += n_waves)
         run_row<PREC, RV, NESTED, KAHAN, DIAG, SHORT, SCHEME>(prm, row, lane, tab, s_tab64, s_ex);
 }

@@ -104,6 +104,15 @@ def test_workspace_size():
     assert M.mlmc_level_workspace_bytes(args) == (16 + 128) * 8 * 8 + 64     # 16 chunks of 64 paths
     args16 = M.level_args(M.gbm(), 5, 1000, M.MLMC_FP16, M.MLMC_NESTED_PWL16)
     assert M.mlmc_level_workspace_bytes(args16) == (8 + 128) * 8 * 8 + 64    # 8 chunks of 128 paths
+    # approximate-only estimators group 8, 4, 2 chunks per row at levels 2, 3, 4, one above
+    for level, rows in ((2, 2), (3, 4), (4, 8), (5, 16)):
+        a = M.level_args(M.gbm(), level, 1000, M.MLMC_FP32, M.MLMC_APPROX_PWL16)
+        assert M.mlmc_level_workspace_bytes(a) == (rows + 128) * 8 * 8 + 64, level
+    # levels 0 and 1 take 8 and 4 chunks per row for every estimator
+    for prec, mode in ((M.MLMC_FP64, M.MLMC_EXACT), (M.MLMC_FP32, M.MLMC_APPROX_PWL16),
+                       (M.MLMC_FP32, M.MLMC_NESTED_PWL16)):
+        a = M.level_args(M.gbm(), 1, 1000, prec, mode)
+        assert M.mlmc_level_workspace_bytes(a) == (4 + 128) * 8 * 8 + 64, mode
 
 
 @pytest.mark.skipif(_gpu_visible(), reason="a GPU is visible")
