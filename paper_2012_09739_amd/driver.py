@@ -10,9 +10,15 @@ squared error eps^2 (variance eps^2 / 2, bias at most eps / sqrt 2) is
     T = 2 eps^-2 (sum_l a_l)^2,   a_l = sqrt(v^_l c^_l)                      (plain)
                                   a_l = sqrt(v-_l c-_l) + sqrt(V-_l C-_l)      (nested)
 
-(Section 3's T^ and T-), so the cheapest mixture takes at every level the option with the
-smallest a_l.  The number of samples of each term j is m_j = 2 eps^-2 sqrt(v_j / c_j)
-sum_k sqrt(v_k c_k) over all terms of all levels.
+(Section 3's T^ and T-), so with costs proportional to the sample counts the cheapest mixture
+takes at every level the option with the smallest a_l.  The number of samples of each term j
+is m_j = 2 eps^-2 sqrt(v_j / c_j) sum_k sqrt(v_k c_k) over all terms of all levels.  A level
+call also has a fixed device cost f (launch, table staging, reduction) that the per-sample
+model leaves out; a nested option pays it twice per level (its two terms are two calls), which
+at large tolerances, where the calls are small, can outweigh what its cheaper samples save.
+The choice therefore minimises T + sum of the chosen calls' f: it starts from the per-level
+minimisers of a_l (and from every single option used at all levels) and changes one level at
+a time while the total falls.
 
 Levels are added until Giles' weak-error test holds: with alpha = 1 (the weak order of
 both Euler-Maruyama and Milstein), max(|E d_L|, |E d_{L-1}| / 2) / (2^alpha - 1) <= eps / sqrt 2,
@@ -61,6 +67,7 @@ class LevelPilot:
     terms (plain: [(v^, c^)]; nested: [(v-, c-), (V-, C-)]) and the exact two-way mean."""
     level: int
     terms: dict = field(default_factory=dict)
+    fixed: dict = field(default_factory=dict)  # per option: the fixed device cost of each term's call
     mean_exact: float = 0.0
 
 
@@ -74,6 +81,35 @@ def cost_weight(terms):
 def choose(pilot):
     """Name of the option with the smallest a_l at this level."""
     return min(pilot.terms, key=lambda k: cost_weight(pilot.terms[k]))
+
+
+def total_time(pilots, choice, eps):
+    """Predicted device time of a per-level choice: the per-sample model T plus the fixed cost
+    of every call it makes (one per term of each level's option)."""
+    flat = [vc for p, name in zip(pilots, choice) for vc in p.terms[name]]
+    fixed = math.fsum(f for p, name in zip(pilots, choice) for f in p.fixed.get(name, ()))
+    return predicted_time(flat, eps) + fixed
+
+
+def choose_levels(pilots, eps):
+    """Per-level option names minimising total_time: the best of the per-level a_l minimisers
+    and of every single option, then single-level changes while the total falls."""
+    names = list(pilots[0].terms)
+    starts = [[choose(p) for p in pilots]] + [[n] * len(pilots) for n in names]
+    best = list(min(starts, key=lambda ch: total_time(pilots, ch, eps)))
+    cur = total_time(pilots, best, eps)
+    improved = True
+    while improved:
+        improved = False
+        for l in range(len(pilots)):
+            for name in names:
+                if name == best[l]:
+                    continue
+                trial = best[:l] + [name] + best[l + 1:]
+                t = total_time(pilots, trial, eps)
+                if t < cur * (1.0 - 1e-12):
+                    best, cur, improved = trial, t, True
+    return best
 
 
 def allocate(terms, eps):
@@ -103,12 +139,14 @@ def _stats(r, term):
 
 
 def _marginal(call, n):
-    """Run n and then 2n samples; returns the 2n-sample result and the device time per extra
-    sample (t(2n) - t(n)) / n, which leaves out the fixed cost of a call (launch, reduction)."""
+    """Run n and then 2n samples; returns the 2n-sample result, the device time per extra
+    sample c = (t(2n) - t(n)) / n, which leaves out the fixed cost of a call (launch,
+    reduction), and that fixed cost t(n) - n c (at least 0)."""
     r1 = call(n)
     r2 = call(2 * n)
     extra = r2["cost_seconds"] - r1["cost_seconds"]
-    return r2, max(extra, 0.05 * r2["cost_seconds"]) / n
+    c = max(extra, 0.05 * r2["cost_seconds"]) / n
+    return r2, c, max(0.0, r1["cost_seconds"] - c * n)
 
 
 def _level(sde, level, n, precision, rv_mode, kahan, seed, scheme):
@@ -123,19 +161,21 @@ def pilot_level(sde, level, options, n, seed, scheme=M.MLMC_SCHEME_EM):
     for opt in options:
         if not opt.nested:
             _level(sde, level, 1024, opt.precision, M.MLMC_EXACT, 0, seed, scheme)
-            r, c = _marginal(lambda k: _level(sde, level, k, opt.precision, M.MLMC_EXACT, 0, seed, scheme), n)
+            r, c, f = _marginal(lambda k: _level(sde, level, k, opt.precision, M.MLMC_EXACT, 0, seed, scheme), n)
             m, v = _stats(r, 0)
             p.terms[opt.name] = [(v, c)]
+            p.fixed[opt.name] = [f]
             p.mean_exact = m
         else:
             approx, nested = opt.rv, opt.rv + 4
             _level(sde, level, 1024, opt.precision, approx, opt.kahan, seed, scheme)
             _level(sde, level, 1024, opt.precision, nested, opt.kahan, seed, scheme)
-            r, c = _marginal(lambda k: _level(sde, level, k, opt.precision, approx, opt.kahan, seed, scheme), n)
+            r, c, f = _marginal(lambda k: _level(sde, level, k, opt.precision, approx, opt.kahan, seed, scheme), n)
             _, v = _stats(r, 0)
-            r, C = _marginal(lambda k: _level(sde, level, k, opt.precision, nested, opt.kahan, seed, scheme), n)
+            r, C, F = _marginal(lambda k: _level(sde, level, k, opt.precision, nested, opt.kahan, seed, scheme), n)
             _, V = _stats(r, 1)
             p.terms[opt.name] = [(v, c), (V, C)]
+            p.fixed[opt.name] = [f, F]
             if not any(not o.nested for o in options):
                 p.mean_exact = _stats(r, 2)[0]
     return p
@@ -165,13 +205,13 @@ def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pil
     """Adaptive MLMC to root-mean-square error eps with a per-level choice among options.
 
     Returns a dict: estimate, its standard error, L, per-level choice, samples per term,
-    the predicted device time of the chosen mixture and of each single option used at every
-    level (the plain binary64 estimator among them), and the measured device time of the
-    final sampling (pilot runs excluded).  concurrent: the final sampling is one level set
+    the predicted device time (per-sample model plus the calls' fixed costs) of the chosen
+    mixture and of each single option used at every level (the plain binary64 estimator among
+    them), and the measured device time of the final sampling (pilot runs excluded).  concurrent: the final sampling is one level set
     (mlmc_level_set_run: every term's call issued together, deep levels first, over several
     streams) and the measured time is its span; otherwise the calls run one after another
-    and the measured time is the sum of their device times, each with a fixed launch and
-    reduction cost of some 20 us that the per-sample model leaves out.  The samples, and so
+    and the measured time is the sum of their device times, each with its fixed launch and
+    reduction cost.  The samples, and so
     the estimate, are the same either way."""
     by_name = {o.name: o for o in options}
     pilots = []
@@ -184,7 +224,7 @@ def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pil
             break
         level += 1
     L = level
-    choice = [choose(p) for p in pilots]
+    choice = choose_levels(pilots, eps)
     flat, where = [], []
     for l, (p, name) in enumerate(zip(pilots, choice)):
         for j, vc in enumerate(p.terms[name]):
@@ -216,12 +256,11 @@ def adaptive_mlmc(sde, eps, options=DEFAULT_OPTIONS, *, l_min=2, l_max=14, n_pil
         parts.append(mean)
         var += v / m
     estimate = math.fsum(parts)
-    single = {}
-    for o in options:
-        terms = [vc for p in pilots for vc in p.terms[o.name]]
-        single[o.name] = predicted_time(terms, eps)
+    single = {o.name: total_time(pilots, [o.name] * len(pilots), eps) for o in options}
     return {"estimate": estimate, "std_error": math.sqrt(var), "L": L, "choice": choice,
             "samples": {"%d/%s/%d" % w: n for w, n in zip(where, counts)},
-            "predicted_seconds": predicted_time(flat, eps), "predicted_seconds_single_option": single,
+            "predicted_seconds": total_time(pilots, choice, eps), "predicted_seconds_single_option": single,
+            "predicted_seconds_per_sample_model": predicted_time(flat, eps),
+            "per_level_fixed_seconds": [dict(p.fixed) for p in pilots],
             "measured_seconds": device_s, "measured_seconds_one_by_one": one_by_one,
             "per_level_a": [{k: cost_weight(v) for k, v in p.terms.items()} for p in pilots]}

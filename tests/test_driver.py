@@ -44,10 +44,11 @@ class FakeLevels:
     """Stands in for mlmc_level_run: sums of n samples equal n * mean and the sums of squares
     n * (var + mean^2), so level_stats returns the prescribed mean and (n/(n-1)) var."""
 
-    def __init__(self, mu=0.05):
+    def __init__(self, mu=0.05, fixed=0.0):
         self.calls = []
         self.schemes = set()
         self.mu = mu
+        self.fixed = fixed  # device seconds every call costs besides its samples
 
     def moments(self, level, precision, mode):
         d = 1e-2 * 2.0 ** -level
@@ -70,7 +71,7 @@ class FakeLevels:
         for k, (mean, var) in enumerate(terms):
             s[k] = n * mean
             q[k] = n * (var + mean * mean)
-        return {"sum": s, "sumsq": q, "n_paths": n, "path_steps": n << level, "cost_seconds": c * n}
+        return {"sum": s, "sumsq": q, "n_paths": n, "path_steps": n << level, "cost_seconds": self.fixed + c * n}
 
     def set_run(self, args_list):
         """Stands in for mlmc_level_set_run: the calls as if run side by side."""
@@ -104,6 +105,35 @@ def test_driver_orchestration_with_synthetic_levels(monkeypatch):
     assert {c[-1] for c in fake.calls} == {0, 1}
     assert out["std_error"] <= eps / math.sqrt(2) * 1.01
     assert fake.schemes == {M.MLMC_SCHEME_EM}
+
+
+def test_total_time_adds_the_fixed_cost_of_every_call():
+    p0 = D.LevelPilot(0, terms={"plain": [(1e-2, 8e-9)], "nested": [(1e-2, 2e-9), (1e-6, 1e-8)]},
+                      fixed={"plain": [2e-5], "nested": [2e-5, 3e-5]})
+    p1 = D.LevelPilot(1, terms={"plain": [(1e-3, 1.6e-8)], "nested": [(1e-3, 4e-9), (1e-7, 2e-8)]},
+                      fixed={"plain": [2e-5], "nested": [2e-5, 3e-5]})
+    eps = 1e-3
+    for choice, fixed in ((["plain", "plain"], 4e-5), (["nested", "plain"], 7e-5), (["nested", "nested"], 1e-4)):
+        flat = [vc for p, n in zip((p0, p1), choice) for vc in p.terms[n]]
+        assert D.total_time([p0, p1], choice, eps) == pytest.approx(D.predicted_time(flat, eps) + fixed, rel=1e-14)
+
+
+@pytest.mark.parametrize("eps,expect_plain", [(3e-2, True), (1e-4, False)])
+def test_choice_weighs_the_fixed_cost_of_a_call(monkeypatch, eps, expect_plain):
+    # nested options make two calls per level: at a large tolerance (few samples) the calls'
+    # fixed cost decides and the plain estimator wins everywhere; at a small one the per-sample
+    # costs decide and the cheapest nested option does
+    fake = FakeLevels(fixed=2e-5)
+    patch(monkeypatch, fake)
+    out = D.adaptive_mlmc(M.gbm(), eps, n_pilot=1 << 12)
+    if expect_plain:
+        assert set(out["choice"]) == {"fp64"}
+    else:
+        assert set(out["choice"]) == {"fp16-cubic-kahan"}
+    assert out["predicted_seconds"] <= min(out["predicted_seconds_single_option"].values()) * (1 + 1e-12)
+    for l, f in enumerate(out["per_level_fixed_seconds"]):
+        assert f["fp64"] == [pytest.approx(2e-5, rel=1e-9)]
+        assert f["fp16-cubic-kahan"] == [pytest.approx(2e-5, rel=1e-9)] * 2
 
 
 def test_driver_passes_the_scheme_to_every_call(monkeypatch):
