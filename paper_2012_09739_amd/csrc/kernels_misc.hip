@@ -99,11 +99,14 @@ int grid_for(uint64_t n, int block) {
 
 }  // namespace
 
+// With one stage block (at most 64 rows) that block writes the result itself: the second stage
+// would add its one row to zeros and return it unchanged (a sum that starts at +0 is never -0),
+// so the bits are those of the two-kernel tree with one launch fewer.
 hipError_t launch_reduce(const double* partials, uint64_t n_rows, double* stage, double* d_out, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_chunks_stage1, dim3(stage_blocks(n_rows)), dim3(kReduceBlock), 0, s, partials, n_rows,
-                       stage);
+    const uint32_t R = stage_blocks(n_rows);
+    hipLaunchKernelGGL(reduce_chunks_stage1, dim3(R), dim3(kReduceBlock), 0, s, partials, n_rows, R == 1 ? d_out : stage);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || R == 1) return e;
     hipLaunchKernelGGL(reduce_chunks_stage2, dim3(1), dim3(kReduceBlock), 0, s, stage, n_rows, d_out);
     return hipGetLastError();
 }
