@@ -182,7 +182,8 @@ int mlmc_level_set_run(const mlmc_level_args_t* args, int n_calls, mlmc_result_t
 /* Asynchronous level call on hip_stream.  args: host.  d_out: device, 8 doubles
  * (sum[0..3], sumsq[0..3]) written when the stream reaches the call.  d_workspace:
  * device scratch of at least mlmc_level_workspace_bytes(args) bytes (8-byte aligned; it
- * holds the chunk partial sums and the stage rows of the fixed-order two-stage reduction,
+ * holds the partial sums of the call's rows of 64-path chunks and the stage rows of the
+ * fixed-order two-stage reduction,
  * all written by the call before they are read), or NULL to use the library's per-device
  * scratch (calls that overlap on one device then race). */
 int mlmc_level_ex(const mlmc_level_args_t* args, double* d_out, void* d_workspace,
