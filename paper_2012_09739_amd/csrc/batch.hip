@@ -684,7 +684,7 @@ int mlmc_batch_autotune(mlmc_batch_t* plan, int repeats, mlmc_batch_cfg_t* best)
     }
     const int steps[] = {64, 256, 1024};
     const int prios[] = {12, 25};
-    const int coops[] = {11, 12, 13, 25};
+    const int coops[] = {11, 12, 13, 14, 25};
     mlmc_batch_cfg_t winner = plan->cfg;
     float best_ms = 1e30f;
     for (const auto& shape : shapes)
