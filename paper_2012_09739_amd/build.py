@@ -25,13 +25,13 @@ RATES_LIB = os.path.join(HERE, "libvalurates.so")
 
 HIP_SOURCES = ["level_f64.hip", "level_f32.hip", "level_f16.hip", "level_bf16.hip",
                "level_milstein_f64.hip", "level_milstein_f32.hip", "level_milstein_f16.hip",
-               "level_milstein_bf16.hip", "kernels_misc.hip", "batch.hip", "mlp_train.hip", "abi.cpp"]
+               "level_milstein_bf16.hip", "level_coop.hip", "kernels_misc.hip", "batch.hip", "mlp_train.hip", "abi.cpp"]
 CXX_SOURCES = ["tables.cpp"]
 # the binary16 instances evaluate each path's variable with scalar binary16 operations, which
 # issue two per clock like binary32 ones; the SLP vectorizer would pack the two paths of a lane
 # into v_pk_* operations (same rate) plus a v_perm per coefficient pair (one slot each)
 EXTRA_FLAGS = {"level_f16.hip": ["-fno-slp-vectorize"], "level_milstein_f16.hip": ["-fno-slp-vectorize"],
-               "batch.hip": ["-fno-slp-vectorize"]}
+               "batch.hip": ["-fno-slp-vectorize"], "level_coop.hip": ["-fno-slp-vectorize"]}
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I" + os.path.join(ROOT, "include"),
           "-I" + CSRC, "-Wall", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]

@@ -422,7 +422,11 @@ int enqueue_level(DevState& st, const mlmc_level_args_t* a, const Variant& v, do
     double* stage = partials + (n_rows == 0 ? 1 : n_rows) * kPartial;
     int grid, block;
     launch_shape(st, n_rows, &grid, &block);
-    if (n_rows > 0) {
+    const bool per_path = out_pf_hat || out_pc_hat || out_pf_bar || out_pc_bar || out_xf_tilde;
+    if (n_rows > 0 && !per_path && coop_level_call(v, a->level, n_rows, st.n_cu)) {
+        e = launch_level_coop(v, p, n_rows, s);
+        if (e != hipSuccess) return hip_fail(e, "cooperative level kernel launch");
+    } else if (n_rows > 0) {
         e = launch_level(v, p, grid, block, s);
         if (e != hipSuccess) return hip_fail(e, "level kernel launch");
     }

@@ -64,6 +64,13 @@ struct Variant {
 
 // Launch helpers implemented in the .hip translation units.
 hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
+// Single-level calls of the nested binary32 estimators (EM, no diagnostic) at level >=
+// kCoopMinLevel with at most kCoopMaxRowsPerCu partial rows per CU run one eight-wave block per
+// chunk (cooperative chunks): same partial rows, same bits, a shorter dependent chain.
+constexpr int kCoopMinLevel = 8;
+constexpr int kCoopMaxRowsPerCu = 4;
+bool coop_level_call(const Variant& v, int level, uint64_t n_rows, int n_cu);
+hipError_t launch_level_coop(const Variant& v, const LevelParams& p, uint64_t n_rows, hipStream_t s);
 hipError_t launch_reduce(const double* partials, uint64_t n_rows, double* stage, double* d_out, hipStream_t s);
 
 // Chunks per partial row.  A row is the unit of the fixed-order reduction: a wave simulates

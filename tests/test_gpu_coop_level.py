@@ -1,0 +1,62 @@
+"""GPU tests of the single-level calls that run one eight-wave block per chunk (nested
+binary32, level >= 8, at most four partial rows per CU): their sums equal bit for bit those of
+the single-wave code (a batch item with cooperative chunks switched off runs that code and the
+same fixed-order reduction), and their terms match the per-path payoffs of the oracle."""
+
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+import mlmc_workloads as W
+from gpu_util import gbm_struct, torch_cuda
+from oracle import fp, mlmc
+from test_gpu_parity import sums_close
+
+import paper_2012_09739_amd as M
+
+pytestmark = pytest.mark.gpu
+
+MODES = {M.MLMC_RV_PWL16: M.MLMC_NESTED_PWL16, M.MLMC_RV_CUBIC16: M.MLMC_NESTED_CUBIC16}
+
+
+def level_call(sde, level, n, rv, kahan, seed):
+    torch = torch_cuda()
+    args = M.level_args(gbm_struct(sde), level, n, M.MLMC_FP32, MODES[rv], kahan, seed)
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    M.mlmc_level_ex(args, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("rv", [M.MLMC_RV_PWL16, M.MLMC_RV_CUBIC16])
+@pytest.mark.parametrize("kahan", [0, 1])
+def test_cooperative_level_calls_equal_the_single_wave_code(rv, kahan):
+    # levels 8..12 with ragged path counts (one to 1024 rows of 64 paths), against one batch
+    # whose items run the single-wave code (coop_level 25: no cooperative chunks)
+    torch = torch_cuda()
+    sde = W.NESTED_FP32["sde"]
+    cases = [(8, 777), (8, 65536), (9, 64), (10, 1000), (11, 65), (12, 3000)]
+    items = [M.item(gbm_struct(sde), l, n, M.MLMC_FP32, kahan, 4, pset=0, stream=1) for l, n in cases]
+    out = torch.zeros((len(items), 8), dtype=torch.float64, device="cuda")
+    plan = M.mlmc_batch_create(items, rv, out, M.mlmc_batch_cfg_t(16, 256, 25, 25, 8))
+    try:
+        M.mlmc_batch_run(plan)
+        torch.cuda.synchronize()
+        single_wave = out.cpu().numpy()
+    finally:
+        M.mlmc_batch_destroy(plan)
+    for (l, n), want in zip(cases, single_wave):
+        np.testing.assert_array_equal(level_call(sde, l, n, rv, kahan, 4), want, err_msg=str((l, n)))
+
+
+@pytest.mark.parametrize("rv", [M.MLMC_RV_PWL16, M.MLMC_RV_CUBIC16])
+def test_cooperative_level_sums_match_oracle(rv):
+    # 200 paths at level 10 (four chunks, the last one ragged): the two-way approximate,
+    # four-way and two-way exact sums against the oracle's per-path terms
+    sde = W.NESTED_FP32["sde"]
+    n, level = 200, 10
+    got = level_call(sde, level, n, rv, 1, 7)
+    o = mlmc.level_paths(level, np.arange(n), sde, rv_mode=mlmc.RV_PWL if rv == M.MLMC_RV_PWL16 else mlmc.RV_CUBIC,
+                         precision=fp.FP32, nested=True, kahan=True, seed=7, stream=1)
+    for k in range(3):
+        assert sums_close(got[k], got[4 + k], o, k), k
