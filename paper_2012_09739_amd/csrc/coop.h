@@ -18,13 +18,15 @@ struct Coop {
     static constexpr int kSteps = 4 * kProducers;  // fine steps per phase
 };
 
-// One cooperative chunk of a nested binary32 item (n_steps >= 4, a multiple of 4) run by
-// the whole block of WAVES waves, P = WAVES - 1 of them producers.  Phase f covers fine steps
-// [4 P f, 4 P f + 4 P): producer wave p draws Philox call P f + p - 1 and writes its four exact
-// (binary64) and approximate (binary32) variables into ring slot f & 1; the consumer, wave 0,
-// reads slot f & 1 while the producers fill slot (f + 1) & 1, and a barrier closes every phase
-// (the same number of barriers in every wave).  The consumer's updates and payoff terms are
-// those of the single-wave code for this variant, in the same order.
+// One cooperative chunk of a nested binary32 item, or (RV = MLMC_RV_EXACT) of the plain
+// binary64 estimator, (n_steps >= 4, a multiple of 4) run by the whole block of WAVES waves,
+// P = WAVES - 1 of them producers.  Phase f covers fine steps [4 P f, 4 P f + 4 P): producer
+// wave p draws Philox call P f + p - 1 and writes its four exact (binary64) and approximate
+// (binary32) variables into ring slot f & 1; the consumer, wave 0, reads slot f & 1 while the
+// producers fill slot (f + 1) & 1, and a barrier closes every phase (the same number of
+// barriers in every wave).  The consumer's updates and payoff terms are those of the
+// single-wave code for this variant, in the same order.  The plain estimator has no
+// approximate pair: ring_b and s_tab are then not used (may be null).
 template <int RV, bool KAHAN, int WAVES>
 __device__ inline void run_chunk_coop(const LevelParams& prm, uint64_t chunk, const float* s_tab, const ExactLds* s_ex,
                                       double (*ring_x)[Coop<WAVES>::kSteps][kWave],
@@ -32,6 +34,7 @@ __device__ inline void run_chunk_coop(const LevelParams& prm, uint64_t chunk, co
     constexpr int kCoopProducers = Coop<WAVES>::kProducers;
     constexpr int kCoopSteps = Coop<WAVES>::kSteps;
     constexpr int DEG = RV == MLMC_RV_CUBIC16 ? 3 : 1;
+    constexpr bool kExactOnly = RV == MLMC_RV_EXACT;
     const uint32_t wave = threadIdx.x / kWave;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t local = chunk * kWave + lane;
@@ -52,7 +55,8 @@ __device__ inline void run_chunk_coop(const LevelParams& prm, uint64_t chunk, co
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     ring_x[f & 1][base + i][lane] = zx[i];
-                    ring_b[f & 1][base + i][lane] = approx_rv<RV, DEG, float, MLMC_FP32>(r.w[i], s_tab, nullptr);
+                    if constexpr (!kExactOnly)
+                        ring_b[f & 1][base + i][lane] = approx_rv<RV, DEG, float, MLMC_FP32>(r.w[i], s_tab, nullptr);
                 }
             }
             __syncthreads();  // phase f written; the consumer is done with slot (f + 1) & 1
@@ -75,6 +79,7 @@ __device__ inline void run_chunk_coop(const LevelParams& prm, uint64_t chunk, co
             em_step<MLMC_SCHEME_EM, double>(Xfh, z, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
             if (coarse) em_step<MLMC_SCHEME_EM, double>(Xch, zh_prev + z, prm.cac_f64, prm.cb_f64, prm.cm_f64, 2.0);
             else zh_prev = z;
+            if constexpr (kExactOnly) continue;
             const float zb = ring_b[f & 1][i][lane];
             if constexpr (KAHAN) {
                 em_step_kahan<MLMC_SCHEME_EM, float>(Xfb, cfb, zb, prm.ca_f32, prm.cb_f32, prm.cm_f32, 1.0f, rnd);
@@ -90,7 +95,7 @@ __device__ inline void run_chunk_coop(const LevelParams& prm, uint64_t chunk, co
         __syncthreads();  // phase f + 1 written; slot f & 1 free again
     }
 
-    // payoffs and differences (binary64), as run_chunk for a nested binary32 chunk
+    // payoffs and differences (binary64), as the single-wave code for the chunk
     double acc[kPartial];
 #pragma unroll
     for (int k = 0; k < kPartial; ++k) acc[k] = 0.0;
@@ -98,12 +103,16 @@ __device__ inline void run_chunk_coop(const LevelParams& prm, uint64_t chunk, co
     double t[kTerms] = {0.0, 0.0, 0.0, 0.0};
     const double pfh = payoff<double>(Xfh, prm.k_f64, prm.payoff);
     const double pch = has_coarse ? payoff<double>(Xch, prm.k_f64, prm.payoff) : 0.0;
-    const float kk = prm.k_f32;
-    const double pfb = (double)payoff<float>(Xfb, kk, prm.payoff, rnd);
-    const double pcb = has_coarse ? (double)payoff<float>(Xcb, kk, prm.payoff, rnd) : 0.0;
-    t[MLMC_TERM_TWO_WAY] = pfb - pcb;
-    t[MLMC_TERM_TWO_WAY_EXACT] = pfh - pch;
-    t[MLMC_TERM_FOUR_WAY] = t[MLMC_TERM_TWO_WAY_EXACT] - t[MLMC_TERM_TWO_WAY];
+    if constexpr (kExactOnly) {
+        t[MLMC_TERM_TWO_WAY] = pfh - pch;
+    } else {
+        const float kk = prm.k_f32;
+        const double pfb = (double)payoff<float>(Xfb, kk, prm.payoff, rnd);
+        const double pcb = has_coarse ? (double)payoff<float>(Xcb, kk, prm.payoff, rnd) : 0.0;
+        t[MLMC_TERM_TWO_WAY] = pfb - pcb;
+        t[MLMC_TERM_TWO_WAY_EXACT] = pfh - pch;
+        t[MLMC_TERM_FOUR_WAY] = t[MLMC_TERM_TWO_WAY_EXACT] - t[MLMC_TERM_TWO_WAY];
+    }
     if (valid) {
 #pragma unroll
         for (int k = 0; k < kTerms; ++k) {

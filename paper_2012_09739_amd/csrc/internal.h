@@ -64,9 +64,10 @@ struct Variant {
 
 // Launch helpers implemented in the .hip translation units.
 hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int block, hipStream_t s);
-// Single-level calls of the nested binary32 estimators (EM, no diagnostic) at level >=
-// kCoopMinLevel with at most kCoopMaxRowsPerCu partial rows per CU run one eight-wave block per
-// chunk (cooperative chunks): same partial rows, same bits, a shorter dependent chain.
+// Single-level calls of the nested binary32 estimators and of the plain binary64 one (EM, no
+// diagnostic) at level >= kCoopMinLevel with at most kCoopMaxRowsPerCu partial rows per CU run
+// one eight-wave block per chunk (cooperative chunks): same partial rows, same bits, a shorter
+// dependent chain.
 constexpr int kCoopMinLevel = 8;
 constexpr int kCoopMaxRowsPerCu = 4;
 bool coop_level_call(const Variant& v, int level, uint64_t n_rows, int n_cu);

@@ -60,3 +60,25 @@ def test_cooperative_level_sums_match_oracle(rv):
                          precision=fp.FP32, nested=True, kahan=True, seed=7, stream=1)
     for k in range(3):
         assert sums_close(got[k], got[4 + k], o, k), k
+
+
+@pytest.mark.parametrize("prec,mode,kahan", [(M.MLMC_FP64, M.MLMC_EXACT, 0), (M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1),
+                                             (M.MLMC_FP32, M.MLMC_NESTED_CUBIC16, 0)])
+def test_cooperative_partial_rows_equal_single_wave_rows(prec, mode, kahan):
+    # 1024 rows of 64 paths (four per CU: cooperative) against 1025 rows (single-wave kernel):
+    # the partial rows of the common paths, read back from the workspaces, agree bit for bit
+    torch = torch_cuda()
+    sde = gbm_struct(W.NESTED_FP32["sde"])
+    # the library takes the cooperative kernel up to four partial rows per CU
+    level, n_coop = 9, 4 * torch.cuda.get_device_properties(0).multi_processor_count * 64
+    rows = {}
+    for n in (n_coop, n_coop + 64):
+        args = M.level_args(sde, level, n, prec, mode, kahan, 11)
+        nb = M.mlmc_level_workspace_bytes(args)
+        ws = torch.full((nb // 8,), float("nan"), dtype=torch.float64, device="cuda")
+        out = torch.zeros(8, dtype=torch.float64, device="cuda")
+        M.mlmc_level_ex(args, out, ws, nb)
+        torch.cuda.synchronize()
+        rows[n] = ws[: (n // 64) * 8].cpu().numpy().reshape(-1, 8)
+    np.testing.assert_array_equal(rows[n_coop], rows[n_coop + 64][: n_coop // 64])
+    assert np.all(np.isfinite(rows[n_coop]))
