@@ -156,16 +156,24 @@ def main():
             for k in (0, 1)}
     out = torch.zeros((2, len(LEVELS), 8), dtype=torch.float64, device="cuda")
     ws_bytes = max(M.mlmc_level_workspace_bytes(x) for x in args[0])
-    ws = torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device="cuda")
+    # the 22 independent level calls, deepest first, alternate between two streams (default
+    # priority), each stream with its own workspace, as mlmc_level_set_run issues a level set:
+    # one call's short coarse kernels and launch gaps overlap the other stream's work
+    side = [torch.cuda.Stream() for _ in range(2)]
+    ws = [torch.empty(ws_bytes // 8 + 1, dtype=torch.float64, device="cuda") for _ in side]
+    order = sorted(((i, l, k) for k in (0, 1) for i, l in enumerate(LEVELS)), key=lambda c: -c[1])
     top = LEVELS[-1]
 
     def step(st):
-        for k in (0, 1):
-            for i, l in enumerate(LEVELS):
-                M.mlmc_level_ex(args[k][i], out[k, i], ws, ws_bytes, st)
+        for s in side:
+            s.wait_stream(st)
+        for j, (i, l, k) in enumerate(order):
+            M.mlmc_level_ex(args[k][i], out[k, i], ws[j % 2], ws_bytes, side[j % 2])
+        for s in side:
+            st.wait_stream(s)
 
-    # one pass (22 level calls, each its level kernel and two reduction kernels) captured once
-    # as a hipGraph and replayed: the GPU work of a step without per-launch host overhead
+    # one pass (22 level calls, each its level kernel and its reduction) captured once as a
+    # hipGraph and replayed: the GPU work of a step without per-launch host overhead
     for _ in range(max(1, a.warmup)):
         step(stream)
     torch.cuda.synchronize()
@@ -194,7 +202,7 @@ def main():
     for _ in range(5):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        M.mlmc_level_ex(args[1][top], out[1, top], ws, ws_bytes, stream)
+        M.mlmc_level_ex(args[1][top], out[1, top], ws[0], ws_bytes, stream)
         e1.record(stream)
         ev.append((e0, e1))
     torch.cuda.synchronize()
@@ -239,7 +247,8 @@ def main():
         "config": {"workload": "nested four-way MLMC, GBM mu=0.05 sigma=0.2 X0=1 T=1, call K=1, "
                                "binary32 approximate pair with piecewise-linear inverse CDF on 16 dyadic "
                                "intervals, binary64 exact pair, levels 0..10, 2^20 paths/level, "
-                               "Kahan off and on; one pass of the 22 level calls replayed as a hipGraph",
+                               "Kahan off and on; one pass of the 22 level calls (deepest first, over two "
+                               "streams) replayed as a hipGraph",
                    "levels": LEVELS, "paths_per_level": N_PATHS, "kahan": [0, 1],
                    "coupled_path_steps_per_step": steps_per_pass, "parallelism": "single GPU"},
         "roofline": roof["fp32"],
