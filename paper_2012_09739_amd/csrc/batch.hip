@@ -12,11 +12,12 @@
 //
 // Cooperative chunks: the chunks of the deepest binary32 items (level >= coop_level) are
 // serial chains of up to 2^24 steps, and one wavefront alone runs them latency bound.  Each
-// block (eight waves) first pops such chunks from a block queue and runs one chunk with all
-// its waves: seven producer waves draw the uniforms and both inverse CDFs for the next phase
-// of 28 steps into an LDS ring while the consumer wave advances the four coupled paths
-// through the current phase, one barrier per phase.  The consumer performs exactly the operations
-// of the single-wave code in the same order, so every sum keeps its bits.
+// block (eight or four waves) first pops such chunks from a block queue and runs one chunk
+// with all its waves (coop.h): seven or three producer waves draw the uniforms and both
+// inverse CDFs for the next phase of 28 or 12 steps into an LDS ring while the consumer wave
+// advances the four coupled paths through the current phase, one barrier per phase.  The
+// consumer performs exactly the operations of the single-wave code in the same order, so
+// every sum keeps its bits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,10 +29,10 @@
 #include <string>
 #include <vector>
 
+#include "coop.h"
 #include "internal.h"
 #include "level_kernel.h"
 #include "reduce.h"
-#include "coop.h"
 
 struct mlmc_batch {
     int device = 0;
