@@ -19,6 +19,9 @@ def test_captured_level_sequence_replays_equal_eager():
     args = [M.level_args(call, l, 50000 + 17 * l, M.MLMC_FP32, M.MLMC_NESTED_PWL16, l % 2, 3) for l in (0, 3, 7)]
     args.append(M.level_args(call, 5, 30000, M.MLMC_FP16, M.MLMC_NESTED_CUBIC16, 1, 3, diag=1))
     args.append(M.level_args(call, 4, 20000, M.MLMC_FP64, M.MLMC_EXACT, 0, 3, scheme=M.MLMC_SCHEME_MILSTEIN))
+    # deep calls with few chunks: one block per chunk (nested binary32, plain binary64)
+    args.append(M.level_args(call, 10, 1000, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1, 3))
+    args.append(M.level_args(call, 9, 777, M.MLMC_FP64, M.MLMC_EXACT, 0, 3))
     out = torch.zeros((len(args), 8), dtype=torch.float64, device="cuda")
     ws = [torch.empty(M.mlmc_level_workspace_bytes(a) // 8 + 1, dtype=torch.float64, device="cuda") for a in args]
     s = torch.cuda.Stream()
@@ -28,6 +31,7 @@ def test_captured_level_sequence_replays_equal_eager():
     torch.cuda.synchronize()
     eager = out.cpu().numpy().copy()
     assert np.all(np.isfinite(eager[:, :3]))
+    assert np.all(np.isfinite(eager[-1, [0, 4]]))
 
     g = torch.cuda.CUDAGraph()
     out.fill_(float("nan"))
