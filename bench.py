@@ -380,12 +380,7 @@ def equal_variance_report(M, E, call):
                                 ("nested_fp32", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0),
                                 ("nested_fp32_kahan", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1)):
         sde = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
-        rows = []
-        for l in LEVELS:
-            M.mlmc_level(sde, l, N_PATHS, prec, mode, k, SEED)  # warm
-            r = M.mlmc_level(sde, l, N_PATHS, prec, mode, k, SEED)
-            rows.append(r)
-        res[name] = rows
+        res[name] = _level_costs(M, sde, LEVELS, N_PATHS, prec, mode, k)
     cost = lambda rows: [r["cost_seconds"] / r["n_paths"] for r in rows]  # noqa: E731
     var = lambda rows, t: [E.level_stats(r["sum"][t], r["sumsq"][t], r["n_paths"])[1] for r in rows]  # noqa: E731
     # per-sample costs without the fixed cost of a call (launch, reduction): what a sample costs
@@ -432,11 +427,16 @@ def _marginal_costs(M, sde, levels, prec, mode, kahan, seed=SEED, reps=3):
     return out
 
 
-def _level_costs(M, sde, levels, n, prec, mode, kahan, seed=SEED):
+def _level_costs(M, sde, levels, n, prec, mode, kahan, seed=SEED, reps=3):
+    """One level call per level (after a warm one) for the sums, with the median device time of
+    `reps` identical calls as its cost (a single small call's time varies by a few us)."""
     rows = []
     for l in levels:
         M.mlmc_level(sde, l, n, prec, mode, kahan, seed)
-        rows.append(M.mlmc_level(sde, l, n, prec, mode, kahan, seed))
+        calls = [M.mlmc_level(sde, l, n, prec, mode, kahan, seed) for _ in range(reps)]
+        r = dict(calls[0])
+        r["cost_seconds"] = sorted(c["cost_seconds"] for c in calls)[reps // 2]
+        rows.append(r)
     return rows
 
 
