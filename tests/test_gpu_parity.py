@@ -207,6 +207,26 @@ def test_nested_sums_match_oracle_terms():
         assert sums_close(got[k], got[4 + k], o, k), k
 
 
+@pytest.mark.parametrize("precision,rv,kahan", [(M.MLMC_FP32, mlmc.RV_PWL, 0), (M.MLMC_FP32, mlmc.RV_PWL, 1),
+                                                (M.MLMC_FP16, mlmc.RV_CUBIC, 1)])
+@pytest.mark.parametrize("level,n", [(2, 3001), (3, 1999), (4, 1000), (5, 777)])
+def test_approximate_sums_match_oracle_terms(level, n, precision, rv, kahan):
+    """Two-way approximate estimators, whose partial rows hold 8, 4, 2 chunks at levels 2, 3, 4
+    (one above): the sums against the oracle's per-path terms, ragged last rows included."""
+    sde = W.GBM_CALL
+    mode = M.MLMC_APPROX_PWL16 if rv == mlmc.RV_PWL else M.MLMC_APPROX_CUBIC16
+    args = M.level_args(M.gbm(payoff=1), level, n, precision, mode, kahan, 6)
+    torch = torch_cuda()
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    M.mlmc_level_ex(args, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    o = mlmc.level_paths(level, np.arange(n), sde, rv_mode=rv, precision=fp.FP32 if precision == M.MLMC_FP32 else fp.FP16,
+                         nested=False, kahan=bool(kahan), seed=6, stream=0)
+    assert sums_close(got[0], got[4], o, 0)
+    assert got[1] == 0 and got[2] == 0 and got[5] == 0 and got[6] == 0
+
+
 def test_full_size_sampled_paths_nested_fp32():
     """2^20 paths at level 10 in the benchmark's launch; oracle recomputes sampled paths."""
     n, level = W.NESTED_FP32["n_paths"], 10
