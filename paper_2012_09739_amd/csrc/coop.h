@@ -67,30 +67,41 @@ __device__ inline void run_chunk_coop(const LevelParams& prm, uint64_t chunk, co
     double Xfh = prm.x0_f64, Xch = prm.x0_f64, zh_prev = 0.0;
     float Xfb = prm.x0_f32, Xcb = Xfb, cfb = 0.0f, ccb = 0.0f, zb_prev = 0.0f;
     const NoRound rnd{};
+    // step i of a phase (phases start at an even step, so odd steps close a coarse step)
+    auto step = [&](int i, double z, float zb) {
+        const bool coarse = (i & 1) != 0;
+        em_step<MLMC_SCHEME_EM, double>(Xfh, z, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
+        if (coarse) em_step<MLMC_SCHEME_EM, double>(Xch, zh_prev + z, prm.cac_f64, prm.cb_f64, prm.cm_f64, 2.0);
+        else zh_prev = z;
+        if constexpr (kExactOnly) return;
+        if constexpr (KAHAN) {
+            em_step_kahan<MLMC_SCHEME_EM, float>(Xfb, cfb, zb, prm.ca_f32, prm.cb_f32, prm.cm_f32, 1.0f, rnd);
+            if (coarse)
+                em_step_kahan<MLMC_SCHEME_EM, float>(Xcb, ccb, rnd(zb_prev + zb), prm.cac_f32, prm.cb_f32, prm.cm_f32,
+                                                     2.0f, rnd);
+        } else {
+            em_step<MLMC_SCHEME_EM, float>(Xfb, zb, prm.ca_f32, prm.cb_f32, prm.cm_f32, 1.0f, rnd);
+            if (coarse) em_step<MLMC_SCHEME_EM, float>(Xcb, rnd(zb_prev + zb), prm.cac_f32, prm.cb_f32, prm.cm_f32, 2.0f, rnd);
+        }
+        if (!coarse) zb_prev = zb;
+    };
     __syncthreads();  // phase 0 written
     for (uint32_t f = 0; f < n_phases; ++f) {
         const uint32_t left = prm.n_steps - f * kCoopSteps;
-        const uint32_t cnt = left < (uint32_t)kCoopSteps ? left : (uint32_t)kCoopSteps;
+        if (left >= (uint32_t)kCoopSteps) {
+            // a full phase, unrolled with no exits: the ring reads of all its steps can be
+            // issued ahead of the dependent updates instead of one LDS round trip per step
+            double z[kCoopSteps];
+            float zb[kCoopSteps];
 #pragma unroll
-        for (int i = 0; i < kCoopSteps; ++i) {
-            if ((uint32_t)i >= cnt) break;
-            const bool coarse = (i & 1) != 0;  // phases start at an even step
-            const double z = ring_x[f & 1][i][lane];
-            em_step<MLMC_SCHEME_EM, double>(Xfh, z, prm.ca_f64, prm.cb_f64, prm.cm_f64, 1.0);
-            if (coarse) em_step<MLMC_SCHEME_EM, double>(Xch, zh_prev + z, prm.cac_f64, prm.cb_f64, prm.cm_f64, 2.0);
-            else zh_prev = z;
-            if constexpr (kExactOnly) continue;
-            const float zb = ring_b[f & 1][i][lane];
-            if constexpr (KAHAN) {
-                em_step_kahan<MLMC_SCHEME_EM, float>(Xfb, cfb, zb, prm.ca_f32, prm.cb_f32, prm.cm_f32, 1.0f, rnd);
-                if (coarse)
-                    em_step_kahan<MLMC_SCHEME_EM, float>(Xcb, ccb, rnd(zb_prev + zb), prm.cac_f32, prm.cb_f32, prm.cm_f32,
-                                                         2.0f, rnd);
-            } else {
-                em_step<MLMC_SCHEME_EM, float>(Xfb, zb, prm.ca_f32, prm.cb_f32, prm.cm_f32, 1.0f, rnd);
-                if (coarse) em_step<MLMC_SCHEME_EM, float>(Xcb, rnd(zb_prev + zb), prm.cac_f32, prm.cb_f32, prm.cm_f32, 2.0f, rnd);
+            for (int i = 0; i < kCoopSteps; ++i) {
+                z[i] = ring_x[f & 1][i][lane];
+                zb[i] = kExactOnly ? 0.0f : ring_b[f & 1][i][lane];
             }
-            if (!coarse) zb_prev = zb;
+#pragma unroll
+            for (int i = 0; i < kCoopSteps; ++i) step(i, z[i], zb[i]);
+        } else {
+            for (int i = 0; i < (int)left; ++i) step(i, ring_x[f & 1][i][lane], kExactOnly ? 0.0f : ring_b[f & 1][i][lane]);
         }
         __syncthreads();  // phase f + 1 written; slot f & 1 free again
     }
