@@ -68,7 +68,7 @@ hipError_t launch_level(const Variant& v, const LevelParams& p, int grid, int bl
 // diagnostic) at level >= kCoopMinLevel with at most kCoopMaxRowsPerCu partial rows per CU run
 // one eight-wave block per chunk (cooperative chunks): same partial rows, same bits, a shorter
 // dependent chain.
-constexpr int kCoopMinLevel = 8;
+constexpr int kCoopMinLevel = 6;
 constexpr int kCoopMaxRowsPerCu = 4;
 bool coop_level_call(const Variant& v, int level, uint64_t n_rows, int n_cu);
 hipError_t launch_level_coop(const Variant& v, const LevelParams& p, uint64_t n_rows, hipStream_t s);

@@ -1,5 +1,5 @@
 """GPU tests of the single-level calls that run one eight-wave block per chunk (nested
-binary32, level >= 8, at most four partial rows per CU): their sums equal bit for bit those of
+binary32 and plain binary64, level >= 6, at most four partial rows per CU): their sums equal bit for bit those of
 the single-wave code (a batch item with cooperative chunks switched off runs that code and the
 same fixed-order reduction), and their terms match the per-path payoffs of the oracle."""
 
@@ -31,11 +31,12 @@ def level_call(sde, level, n, rv, kahan, seed):
 @pytest.mark.parametrize("rv", [M.MLMC_RV_PWL16, M.MLMC_RV_CUBIC16])
 @pytest.mark.parametrize("kahan", [0, 1])
 def test_cooperative_level_calls_equal_the_single_wave_code(rv, kahan):
-    # levels 8..12 with ragged path counts (one to 1024 rows of 64 paths), against one batch
-    # whose items run the single-wave code (coop_level 25: no cooperative chunks)
+    # levels 6..12 with ragged path counts (one to 1024 rows of 64 paths; level 6 ends on a
+    # partial phase of 8 steps), against one batch whose items run the single-wave code
+    # (coop_level 25: no cooperative chunks)
     torch = torch_cuda()
     sde = W.NESTED_FP32["sde"]
-    cases = [(8, 777), (8, 65536), (9, 64), (10, 1000), (11, 65), (12, 3000)]
+    cases = [(6, 129), (7, 4000), (8, 777), (8, 65536), (9, 64), (10, 1000), (11, 65), (12, 3000)]
     items = [M.item(gbm_struct(sde), l, n, M.MLMC_FP32, kahan, 4, pset=0, stream=1) for l, n in cases]
     out = torch.zeros((len(items), 8), dtype=torch.float64, device="cuda")
     plan = M.mlmc_batch_create(items, rv, out, M.mlmc_batch_cfg_t(16, 256, 25, 25, 8))
@@ -64,13 +65,14 @@ def test_cooperative_level_sums_match_oracle(rv):
 
 @pytest.mark.parametrize("prec,mode,kahan", [(M.MLMC_FP64, M.MLMC_EXACT, 0), (M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1),
                                              (M.MLMC_FP32, M.MLMC_NESTED_CUBIC16, 0)])
-def test_cooperative_partial_rows_equal_single_wave_rows(prec, mode, kahan):
+@pytest.mark.parametrize("level", [6, 9])
+def test_cooperative_partial_rows_equal_single_wave_rows(prec, mode, kahan, level):
     # 1024 rows of 64 paths (four per CU: cooperative) against 1025 rows (single-wave kernel):
     # the partial rows of the common paths, read back from the workspaces, agree bit for bit
     torch = torch_cuda()
     sde = gbm_struct(W.NESTED_FP32["sde"])
     # the library takes the cooperative kernel up to four partial rows per CU
-    level, n_coop = 9, 4 * torch.cuda.get_device_properties(0).multi_processor_count * 64
+    n_coop = 4 * torch.cuda.get_device_properties(0).multi_processor_count * 64
     rows = {}
     for n in (n_coop, n_coop + 64):
         args = M.level_args(sde, level, n, prec, mode, kahan, 11)
