@@ -67,11 +67,11 @@ ROOFLINE_KERNELS = {
                  kernel="level_kernel<FP16, CUBIC16, nested, Kahan> at level 6 (2^24 paths x 64 steps)"),
 }
 # the sources and build flags the counts above were taken from (sha256 of ISA_SOURCES)
-ISA_SOURCES_SHA256 = "af2ed6b32ccc40c3f61a79d35db277c90aa368163f01fad1bfac22cfe603c421"
+ISA_SOURCES_SHA256 = "66e051ae0572e5bdafd00bc7e2e43ce7b6c4ecbbbcdfb3137aa73c03fe74e7c7"
 # HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB;
 # scale factors from a 256 MiB device copy), valid for the kernel sources hashed below
 TRAFFIC_BYTES_PER_LAUNCH = {"fp32": (218.438 * 2.0 + 1024.0) * 1024, "fp16": (243.938 * 2.0 + 8192.0) * 1024}
-TRAFFIC_SOURCES_SHA256 = "b2b23f31ff7b5902c9918d4d4e9ac12442391b13d0ee3b6dd79b1c52c2feb347"
+TRAFFIC_SOURCES_SHA256 = "9db52fa51560ac6e26823a97d2be99711adc8cba1834fd23d181707384d88fe8"
 # what a kernel's instructions depend on: its sources and the build flags
 ISA_SOURCES = ("csrc/level_kernel.h", "csrc/level_launch.h", "csrc/icdf.h", "csrc/philox.h", "csrc/mlp.h",
                "csrc/internal.h", "csrc/level_f32.hip", "csrc/level_f16.hip", "csrc/icdf_exact_coeffs.h", "build.py")

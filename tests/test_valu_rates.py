@@ -34,6 +34,16 @@ def test_op_list_matches_bench():
     assert n == len(bench.VALU_OPS)
 
 
+def test_roofline_counts_belong_to_the_current_sources():
+    # bench.py's issue counts (slots per path-step) and counter traffic were taken from the
+    # roofline kernels' sources as they are now; a change to any of those files must re-count
+    # the step loop's assembly (or show it unchanged) and refresh the hashes, else the bench
+    # line reports those figures as null
+    import bench
+    assert bench.sources_sha256(bench.ISA_SOURCES) == bench.ISA_SOURCES_SHA256
+    assert bench.kernel_sources_sha256() == bench.TRAFFIC_SOURCES_SHA256
+
+
 @pytest.mark.parametrize("op,waves,iters", [(-1, 8, 16), (99, 8, 16), (0, 0, 16), (0, 9, 16), (0, 8, 0),
                                             (0, 8, (1 << 20) + 1)])
 def test_invalid_arguments(op, waves, iters):
