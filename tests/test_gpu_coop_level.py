@@ -51,11 +51,11 @@ def test_cooperative_level_calls_equal_the_single_wave_code(rv, kahan):
 
 
 @pytest.mark.parametrize("rv", [M.MLMC_RV_PWL16, M.MLMC_RV_CUBIC16])
-def test_cooperative_level_sums_match_oracle(rv):
-    # 200 paths at level 10 (four chunks, the last one ragged): the two-way approximate,
-    # four-way and two-way exact sums against the oracle's per-path terms
+@pytest.mark.parametrize("level,n", [(10, 200), (6, 129)])
+def test_cooperative_level_sums_match_oracle(rv, level, n):
+    # a few chunks, the last one ragged (level 6: 64 steps, two full phases and one of 8): the
+    # two-way approximate, four-way and two-way exact sums against the oracle's per-path terms
     sde = W.NESTED_FP32["sde"]
-    n, level = 200, 10
     got = level_call(sde, level, n, rv, 1, 7)
     o = mlmc.level_paths(level, np.arange(n), sde, rv_mode=mlmc.RV_PWL if rv == M.MLMC_RV_PWL16 else mlmc.RV_CUBIC,
                          precision=fp.FP32, nested=True, kahan=True, seed=7, stream=1)
@@ -84,3 +84,16 @@ def test_cooperative_partial_rows_equal_single_wave_rows(prec, mode, kahan, leve
         rows[n] = ws[: (n // 64) * 8].cpu().numpy().reshape(-1, 8)
     np.testing.assert_array_equal(rows[n_coop], rows[n_coop + 64][: n_coop // 64])
     assert np.all(np.isfinite(rows[n_coop]))
+
+
+@pytest.mark.parametrize("level,n", [(6, 1000), (7, 333)])
+def test_cooperative_plain_fp64_sums_match_oracle(level, n):
+    # the plain binary64 estimator through the cooperative kernel (at most four rows per CU)
+    # against the oracle's per-path two-way terms
+    sde = W.PLAIN_FP64["sde"]
+    seed = W.PLAIN_FP64["seed"]
+    r = M.mlmc_level(gbm_struct(sde), level, n, M.MLMC_FP64, M.MLMC_EXACT, 0, seed)
+    o = mlmc.level_paths(level, np.arange(n), sde, rv_mode=mlmc.RV_EXACT, precision=fp.FP64, nested=False,
+                         kahan=False, seed=seed)
+    assert sums_close(r["sum"][0], r["sumsq"][0], o, 0)
+    assert r["path_steps"] == n * 2 ** level
