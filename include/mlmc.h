@@ -157,7 +157,7 @@ int mlmc_shutdown(void);
  * Philox stream 0 for MLMC_EXACT / MLMC_APPROX_*, 1 for MLMC_NESTED_* (so the two sums
  * of theta- are independent), pset 0, path_offset 0.  out: host, filled on success,
  * including the device time of the call.  Runs on a library-owned stream.  The sums do not
- * depend on how the call is launched: a deep level (>= 8) with few 64-path chunks (at most
+ * depend on how the call is launched: a level >= 6 with few 64-path chunks (at most
  * four per CU) of the nested binary32 or the plain binary64 estimator runs one block of eight
  * waves per chunk instead of one wave, with the same partial sums and the same bits. */
 int mlmc_level(const mlmc_gbm_t* sde, int level, uint64_t n_paths, int precision,
