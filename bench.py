@@ -24,6 +24,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -124,9 +125,10 @@ def parse():
                    help="comma-separated report legs to run: " + ", ".join(REPORT_LEGS))
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a device copy of known size (HBM counter calibration)")
-    p.add_argument("--profile", choices=("roofline", "valu_rates"),
-                   help="profiling run: only the dominant kernels' timed launches (roofline) or only "
-                        "the issue-rate probes, printed as one JSON line without the headline metric")
+    p.add_argument("--profile", choices=("roofline", "valu_rates", "coop"),
+                   help="profiling run: only the dominant kernels' timed launches (roofline), only "
+                        "the issue-rate probes, or only deep single-level calls with few chunks "
+                        "(cooperative kernel), printed as one JSON line without the headline metric")
     return p.parse_args()
 
 
@@ -285,19 +287,19 @@ def equal_variance_summary(extra):
 
 
 def profile_run(what, calibrate_copy):
-    """The launches a rocprofv3 summary of the roofline numbers covers: the dominant kernels
-    exactly as roofline_block times them (2 warm-up and 10 timed launches each, nothing else
-    on the device), or the issue-rate probes."""
+    """The launches a rocprofv3 summary covers: the dominant kernels exactly as roofline_block
+    times them (2 warm-up and 10 timed launches each, nothing else on the device), the
+    cooperative kernel of deep single-level calls with few chunks, or the issue-rate probes."""
     import torch
 
     import paper_2012_09739_amd as M
     torch.cuda.set_device(0)
     M.mlmc_init(0)
     line = {"profile": what}
-    if what == "roofline":
-        # the timed launches follow about a second of the same kind of load (the kernel's
-        # instance without Kahan updates, a separate entry in a profiler's statistics), as in
-        # the full run, where they follow the headline sweep: the shader clock settles first
+    if what in ("roofline", "coop"):
+        # the timed launches follow about a second of the same kind of load (the binary32
+        # level-10 kernel without Kahan updates, a separate entry in a profiler's statistics),
+        # as in the full run, where they follow the headline sweep: the shader clock settles first
         call = M.gbm(payoff=M.MLMC_PAYOFF_CALL)
         warm = M.level_args(call, 10, N_PATHS, M.MLMC_FP32, M.MLMC_NESTED_PWL16, 0, SEED)
         t0 = time.perf_counter()
@@ -305,6 +307,7 @@ def profile_run(what, calibrate_copy):
             for _ in range(50):
                 M.mlmc_paths(warm)
             torch.cuda.synchronize()
+    if what == "roofline":
         for key in ROOFLINE_KERNELS:
             line["roofline" if key == "fp32" else "roofline_" + key] = roofline_block(M, torch, key)
         if calibrate_copy:
@@ -314,6 +317,17 @@ def profile_run(what, calibrate_copy):
                 dst.copy_(src)
             torch.cuda.synchronize()
             line["copy_calibration_bytes"] = 2 * src.numel() * 4
+    elif what == "coop":
+        # 256 chunks of 64 paths at level 14 (one per CU): each runs one eight-wave block,
+        # seven producer waves ahead of one consumer wave; 2 warm-up and 5 timed calls each
+        n, level = 256 * 64, 14
+        for tag, prec, mode, kahan in (("nested_fp32_pwl16_kahan", M.MLMC_FP32, M.MLMC_NESTED_PWL16, 1),
+                                       ("plain_fp64", M.MLMC_FP64, M.MLMC_EXACT, 0)):
+            for _ in range(2):
+                M.mlmc_level(call, level, n, prec, mode, kahan, SEED)
+            ts = [M.mlmc_level(call, level, n, prec, mode, kahan, SEED)["cost_seconds"] for _ in range(5)]
+            line[tag] = {"level": level, "n_paths": n, "call_ms": [t * 1e3 for t in ts],
+                         "ns_per_step": statistics.median(ts) * 1e9 / 2 ** level}
     else:
         line["valu_issue_rates"] = valu_rates()
     print(json.dumps(line), flush=True)
